@@ -1,0 +1,277 @@
+"""Pins for the CPU oracle: paper examples, closed forms, a library routine
+(Python's ``re``), brute force and invariants.  CPU only."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import brute, compose, subset, tagset
+from workloads.regex import regex_nfa
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def as_set(m):
+    return {tuple(int(v) for v in r) for r in np.asarray(m).reshape(-1, 3)}
+
+
+def as_list(m):
+    return [tuple(int(v) for v in r) for r in np.asarray(m).reshape(-1, 3)]
+
+
+def fig2_golden():
+    rows = []
+    with open(os.path.join(GOLDEN, "fig2_aacacab.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(tuple(int(v) for v in line.split()))
+    return rows
+
+
+# ---------------------------------------------------------------- paper examples
+
+FIG1_REGEXES = [(b"a*c", 0), (b"ac", 1), (b"a(ca)*b", 2)]
+
+
+@pytest.mark.parametrize("build", ["hand", "regex", "subset_dfa"])
+def test_fig2_match_set(build):
+    """Fig. 2: exactly the ten printed matches, whatever automaton encodes Fig. 1."""
+    fsm = {"hand": W.fig1_nfa, "regex": lambda: regex_nfa(FIG1_REGEXES),
+           "subset_dfa": lambda: subset.to_dfa(W.fig1_nfa())}[build]()
+    got, _ = oracle.scan(fsm, W.FIG2_INPUT)
+    assert as_list(got) == sorted(fig2_golden())
+
+
+def test_fig2_online_order_of_paper_algorithm():
+    """The paper's tagged algorithm reports online in Fig. 2's printing order."""
+    assert tagset.run(W.fig1_nfa(), W.FIG2_INPUT) == fig2_golden()
+
+
+def test_fig3h_three_matches_ending_at_index_1():
+    """Fig. 3(h): running Fig. 1's PFSM on "ac" finds three matches ending at 1."""
+    got = as_list(oracle.scan(W.fig1_nfa(), b"ac")[0])
+    assert len([m for m in got if m[1] == 1]) == 3
+    assert got == [(0, 1, 0), (0, 1, 1), (1, 1, 0)]
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 64, 300])
+def test_sigma_plus_every_substring(n):
+    """Sigma+ accepts every non-empty substring: n(n+1)/2 matches, one per (s, e)."""
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, 256, n, dtype=np.uint8)
+    got, work = oracle.scan(W.sigma_plus_dfa(), x)
+    assert len(got) == n * (n + 1) // 2
+    assert as_set(got) == {(s, e, 0) for s in range(n) for e in range(s, n)}
+    # every instance survives to the end of the input: T = X = n(n+1)/2
+    assert work["T"] == work["X"] == n * (n + 1) // 2
+
+
+def test_sigma_plus_bound_with_label_set():
+    """|M| <= |L| * n(n+1)/2 (Section III.C), reached with three labels on one state."""
+    n = 50
+    got, _ = oracle.scan(W.sigma_plus_dfa((4, 1, 9)), bytes(n))
+    assert len(got) == 3 * n * (n + 1) // 2
+    assert as_list(got)[:3] == [(0, 0, 1), (0, 0, 4), (0, 0, 9)]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 100])
+def test_a_plus_on_a_power_n(n):
+    fsm = regex_nfa([(b"a+", 3)])
+    got, _ = oracle.scan(fsm, b"a" * n)
+    assert len(got) == n * (n + 1) // 2
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 100])
+def test_literal_aa_on_a_power_n(n):
+    got, work = oracle.scan(W.literal_dfa(b"aa"), b"a" * n)
+    assert as_list(got) == [(s, s + 1, 0) for s in range(n - 1)]
+    # each start reads 'a', 'a' (final), then a third symbol that has no
+    # transition out of the final state: min(3, n - s) symbols
+    assert work["T"] == sum(min(3, n - s) for s in range(n))
+
+
+def naive_occurrences(hay: bytes, needle: bytes):
+    out, i = [], hay.find(needle)
+    while i >= 0:
+        out.append(i)
+        i = hay.find(needle, i + 1)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_literal_equals_overlapping_search(seed):
+    """One literal pattern reports exactly the overlapping occurrences bytes.find finds."""
+    rng = np.random.default_rng(seed)
+    needle = bytes(rng.choice(list(b"ab"), int(rng.integers(1, 5))))
+    hay = bytes(rng.choice(list(b"abc"), 3000))
+    got = as_list(oracle.scan(W.literal_dfa(needle, 7), hay)[0])
+    assert got == [(i, i + len(needle) - 1, 7) for i in naive_occurrences(hay, needle)]
+
+
+# ---------------------------------------------------------------- library routine: re
+
+REGEXES = [b"a*c", b"ac", b"a(ca)*b", b"(ab|a)*b{1,3}", b"[a-c]+d?", b"a.{0,3}b", b"(a|b)*abb",
+           b"[^a]b*", b"(a|ab)(c|bcd)", b"a?a?a?aaa", b"((a|b)(c|d))+", b"d{2,}", b"(a*)*b"]
+
+
+@pytest.mark.parametrize("pat", REGEXES)
+def test_matches_re_fullmatch(pat):
+    """Every (s, e) with re.fullmatch(pattern, x[s..e]) and nothing else."""
+    rng = np.random.default_rng(len(pat))
+    fsm = regex_nfa([(pat, 11)])
+    for _ in range(8):
+        x = bytes(rng.choice(list(b"abcd"), 40))
+        got = as_list(oracle.scan(fsm, x)[0])
+        ref = sorted((s, e, 11) for s in range(len(x)) for e in range(s, len(x))
+                     if re.fullmatch(pat, x[s:e + 1], re.DOTALL))
+        assert got == ref
+
+
+def test_regex_union_matches_re():
+    """A union of expressions (Section III.A) reports each expression's matches with its label."""
+    pats = [(REGEXES[i], 100 + i) for i in range(0, len(REGEXES), 2)]
+    fsm = regex_nfa(pats)
+    rng = np.random.default_rng(5)
+    x = bytes(rng.choice(list(b"abcd"), 60))
+    got = as_list(oracle.scan(fsm, x)[0])
+    ref = sorted((s, e, lab) for s in range(len(x)) for e in range(s, len(x)) for p, lab in pats
+                 if re.fullmatch(p, x[s:e + 1], re.DOTALL))
+    assert got == ref
+
+
+# ---------------------------------------------------------------- brute force
+
+def _small_dfa(seed):
+    rng = np.random.default_rng(seed)
+    return W.random_dfa(rng, int(rng.integers(1, 7)), int(rng.integers(1, 4)), p_dead=0.35,
+                        n_finals=int(rng.integers(1, 4)), max_labels=2, n_labels=3), rng
+
+
+def _small_nfa(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 8))
+    return W.random_nfa(rng, n, list(b"abc"), n_edges=int(rng.integers(0, 3 * n + 2)),
+                        p_eps=0.25, n_finals=int(rng.integers(1, 4))), rng
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_dfa_vs_brute_force(seed):
+    fsm, rng = _small_dfa(seed)
+    x = bytes(rng.choice(list(b"abcd"), int(rng.integers(0, 28))))
+    ref = brute.matches(fsm, x)
+    for prune in (True, False):
+        assert as_list(oracle.scan(fsm, x, prune=prune, threads=3)[0]) == ref
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_nfa_vs_brute_force(seed):
+    fsm, rng = _small_nfa(seed)
+    x = bytes(rng.choice(list(b"abcd"), int(rng.integers(0, 28))))
+    ref = brute.matches(fsm, x)
+    for prune in (True, False):
+        for memo in (True, False):
+            assert as_list(oracle.scan(fsm, x, prune=prune, memo=memo, threads=2)[0]) == ref
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_paper_algorithm_vs_brute_force(seed):
+    """The tagged four-step algorithm (Section III.B) reaches the plain definition."""
+    fsm, rng = _small_nfa(seed)
+    x = bytes(rng.choice(list(b"abc"), 20))
+    assert sorted(tagset.run(fsm, x)) == brute.matches(fsm, x)
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("seed", range(12))
+def test_nfa_equals_subset_dfa(seed):
+    """An NFA and the DFA of its subset construction (Section II) report the same matches."""
+    rng = np.random.default_rng(77 + seed)
+    fsm = W.random_nfa(rng, 10, list(b"abcd"), n_edges=24, p_eps=0.2, n_finals=3)
+    dfa = subset.to_dfa(fsm)
+    x = bytes(rng.choice(list(b"abcde"), 3000))
+    assert np.array_equal(oracle.scan(fsm, x)[0], oracle.scan(dfa, x)[0])
+
+
+def test_union_is_union_of_match_sets():
+    """Union through an ancillary initial state (Section III.A) reports the union."""
+    rng = np.random.default_rng(3)
+    parts = [W.random_nfa(rng, 6, list(b"abc"), 14, n_labels=1) for _ in range(3)]
+    for i, p in enumerate(parts):  # distinct labels per part
+        p.final_labels = p.final_labels * 0 + 10 * i
+    parts.append(W.random_dfa(rng, 5, 3, p_dead=0.3, n_labels=1))
+    parts[-1].final_labels = parts[-1].final_labels * 0 + 99
+    x = bytes(rng.choice(list(b"abcd"), 2000))
+    u = compose.union(parts)
+    whole = as_set(oracle.scan(u, x)[0])
+    assert whole == set().union(*(as_set(oracle.scan(p, x)[0]) for p in parts))
+
+
+def test_drop_label_equals_filtered():
+    """Removing an expression's label removes exactly its matches."""
+    wl = W.cfg3(seed=41, n=1 << 16, n_patterns=60, plant_rate=2e-3)
+    full, _ = oracle.scan(wl.automaton, wl.data)
+    lab = int(full[0, 2])
+    a = wl.automaton
+    keep = a.final_labels != lab
+    off = np.zeros_like(a.final_off)
+    for q in range(a.n_states):
+        off[q + 1] = off[q] + int(keep[a.final_off[q]:a.final_off[q + 1]].sum())
+    b = W.NFA(a.n_states, a.q0, a.n_classes, a.row_ptr, a.edge_class, a.edge_dst, a.class_bits,
+              off, a.final_labels[keep])
+    assert np.array_equal(oracle.scan(b, wl.data)[0], compose.drop_label(full, lab))
+
+
+@pytest.mark.parametrize("cuts", [[0, 100, 101, 5000, 8192], [0, 1, 2, 3, 8192], [0, 4096, 8192]])
+def test_segment_split_equals_whole(cuts):
+    """Lazy data partitioning (Section III.D.2): segments own their starts and read past
+    their end; the concatenation equals the whole."""
+    wl = W.cfg1(seed=9, n=8192)
+    whole, _ = oracle.scan(wl.automaton, wl.data)
+    pieces = [oracle.scan(wl.automaton, wl.data, s_lo=a, s_hi=b)[0] for a, b in zip(cuts, cuts[1:])]
+    assert np.array_equal(np.concatenate(pieces), whole)
+
+
+def test_shortcuts_and_threads_do_not_change_results():
+    wl = W.cfg3(seed=12, n=1 << 15, n_patterns=80, plant_rate=3e-3)
+    ref, _ = oracle.scan(wl.automaton, wl.data, prune=False, memo=False, threads=1)
+    assert len(ref) > 10
+    for prune in (True, False):
+        for memo in (True, False):
+            for th in (1, 5):
+                got, _ = oracle.scan(wl.automaton, wl.data, prune=prune, memo=memo, threads=th)
+                assert np.array_equal(got, ref)
+
+
+def test_output_sorted_unique_and_in_range():
+    wl = W.cfg2(seed=8, n=1 << 18)
+    m, work = oracle.scan(wl.automaton, wl.data)
+    keys = m[:, 0].astype(np.int64) << 40 | m[:, 1].astype(np.int64) << 8 | m[:, 2]
+    assert np.all(np.diff(keys) > 0)
+    assert np.all((0 <= m[:, 0]) & (m[:, 0] <= m[:, 1]) & (m[:, 1] < wl.data.size))
+    # each planted walk ends in a final state: a match at (plant start, plant end)
+    s = as_set(m)
+    starts = {(a, a + ln - 1) for a, ln in wl.meta["plants"]}
+    assert starts <= {(a, b) for a, b, _ in s}
+    assert work["T"] >= wl.data.size
+
+
+def test_empty_input_and_empty_matches_never_reported():
+    # q0 is final (label 5) and has a self loop on 'a': no zero-length matches
+    fsm = regex_nfa([(b"a*", 5)])
+    assert as_list(oracle.scan(fsm, b"")[0]) == []
+    assert as_list(oracle.scan(fsm, b"b")[0]) == []
+    assert as_list(oracle.scan(fsm, b"aa")[0]) == [(0, 0, 5), (0, 1, 5), (1, 1, 5)]
+
+
+def test_invalid_descriptor_rejected():
+    d = W.literal_dfa(b"ab")
+    d.delta = d.delta.copy()
+    d.delta[3] = 99
+    with pytest.raises(ValueError):
+        oracle.scan(d, b"ab")
