@@ -1,0 +1,207 @@
+/*
+ * pfsm.h -- C ABI of libpfsm, an all-matches Parallel Finite State Machine
+ * scanner for AMD Instinct MI355X (gfx950).
+ *
+ * A PFSM (Section III.A) is the tuple (Sigma, Q, q0, delta, F, L, l): an
+ * automaton whose transition function may be deterministic or not, whose
+ * final states carry labels naming the regular expression they accept, and
+ * which is run with a fresh instance started at every input position
+ * (Section III.B).  A scan reports every match as a triple
+ * (start, end, label): the instance started at `start` entered, after
+ * consuming input[end], a final state labelled `label` (Section III.B,
+ * reporting rule; Fig. 2 lists such triples).  Overlapping and nested
+ * matches are all reported.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Positions are 0-based, `end` is inclusive, 0 <= start <= end < n.
+ *   Empty matches are never reported: a match consumes at least one byte.
+ * - The match set is a set: each (start, end, label) appears once, even when
+ *   several final states carrying the same label are entered at once.
+ * - Output order is ascending (start, end, label).
+ * - Labels are int32 >= 0.  A final state may carry several labels (a label
+ *   set); a state with an empty label set is not final.
+ * - Every call returns PFSM_OK (0) or a negative PFSM_E* code and never
+ *   throws across the ABI.  pfsm_last_error() returns a description of the
+ *   calling thread's most recent failure.
+ * - Streams: every `hip_stream` argument is a hipStream_t (NULL = the null
+ *   stream).  All device work of a call is ordered on that stream.
+ * - Ownership: the library copies every host descriptor array during the
+ *   call; the caller keeps ownership of them.  Device input and output
+ *   buffers belong to the caller and are never freed by the library.  The
+ *   handle owns its device tables and per-stream scan workspaces until
+ *   pfsm_free().
+ * - Threads: one handle must not be mutated (add/remove/free) concurrently
+ *   with any other call on it.  Scans on one handle issued on different
+ *   streams may overlap; scans on the same stream run in stream order.
+ */
+#ifndef PFSM_H
+#define PFSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfsm pfsm_t;
+
+/* One match: 0-based positions, end inclusive (Fig. 2 prints [start-end]). */
+typedef struct {
+    int32_t start, end, label;
+} pfsm_match_t;
+
+/* A DFA (Section II: (Sigma, Q, q0, delta, F)) with labelled final states
+ * (Section III.A: L and l).
+ *   n_states        |Q|, >= 1; q0 in [0, n_states).
+ *   n_symbols       |Sigma|, >= 1, n_states * n_symbols < 2^31.
+ *   byte_to_symbol  [256] host array: symbol of each input byte, or -1 when
+ *                   the byte is not in Sigma (an instance reading it ends).
+ *                   NULL means the identity map and requires n_symbols == 256.
+ *   delta           [n_states * n_symbols] host array, row-major
+ *                   (delta[q * n_symbols + s]); a target state or -1 for "no
+ *                   transition" (the instance ends).  Used as given.
+ *   final_off       [n_states + 1] host array, CSR offsets into final_labels;
+ *                   final_off[0] == 0, non-decreasing.
+ *   final_labels    [final_off[n_states]] host array: the label set of each
+ *                   state (duplicates allowed, reported once).            */
+typedef struct {
+    int32_t n_states, n_symbols, q0;
+    const int16_t *byte_to_symbol;
+    const int32_t *delta;
+    const int32_t *final_off, *final_labels;
+} pfsm_dfa_desc;
+
+/* An NFA (Section II: delta: Q x Sigma -> P(Q)) with epsilon edges and
+ * labelled final states, as CSR successor lists over byte classes.
+ *   n_states        |Q| >= 1; q0 in [0, n_states).
+ *   n_classes       number of byte classes (>= 0).
+ *   row_ptr         [n_states + 1] CSR offsets; row_ptr[0] == 0.
+ *   edge_class      [row_ptr[n_states]] class of each edge: -1 = epsilon,
+ *                   k in [0, n_classes) = the byte set class_bits[k*8..k*8+7].
+ *   edge_dst        [row_ptr[n_states]] target state of each edge.
+ *   class_bits      [n_classes * 8] 256-bit byte sets: byte b is in class k
+ *                   when bit (b % 32) of class_bits[k * 8 + b / 32] is set.
+ *   final_off, final_labels  label sets, as for the DFA.
+ * Epsilon edges taken right after a byte is consumed count for that byte's
+ * position: a final state reached through them is reported with end = the
+ * position of that byte.                                                   */
+typedef struct {
+    int32_t n_states, q0, n_classes;
+    const int32_t *row_ptr, *edge_class, *edge_dst;
+    const uint32_t *class_bits;
+    const int32_t *final_off, *final_labels;
+} pfsm_nfa_desc;
+
+/* Work counters of the most recent scan on a stream (pfsm_last_stats).
+ *   transitions  instance-steps: over all start positions, the number of
+ *                bytes consumed while the instance had a live state (the
+ *                byte that ends it included).  A state is live when some
+ *                final state with an enabled label is reachable from it.
+ *   activations  live states entered, summed over those steps.
+ *   matches      the scan's match count.
+ *   long_walks   instances that outlived their window's staged bytes.   */
+typedef struct {
+    int64_t transitions, activations, matches, long_walks;
+} pfsm_stats;
+
+enum {
+    PFSM_OK = 0,
+    PFSM_EINVAL = -1,    /* malformed descriptor or argument               */
+    PFSM_ENOMEM = -2,    /* host or device allocation failed               */
+    PFSM_EOVERFLOW = -3, /* more matches than `cap`; count still reported  */
+    PFSM_EHIP = -4,      /* a HIP runtime call failed                      */
+    PFSM_ENOENT = -5,    /* no pattern carries the label                   */
+    PFSM_EEXIST = -6,    /* a pattern already carries the label            */
+    PFSM_ENOSYS = -7     /* operation not supported for this handle kind   */
+};
+
+/* Load a DFA (Section II) as a PFSM.  The transition table is kept as given
+ * (narrowed to 16-bit storage when n_states < 32768, values unchanged); the
+ * library derives read-only caches from it (live flags, the row of q0 per
+ * byte, label CSR).  On success *out owns the device copy.  Synchronises
+ * `hip_stream` before returning.
+ * Errors: PFSM_EINVAL (descriptor), PFSM_ENOMEM, PFSM_EHIP.               */
+int pfsm_load_dfa(pfsm_t **out, const pfsm_dfa_desc *d, void *hip_stream);
+
+/* Load an NFA (Section II/III.A) as a PFSM, for instance the union of
+ * several expressions under an ancillary initial state with epsilon edges
+ * (Section III.A).  No conversion to a DFA takes place.  Synchronises
+ * `hip_stream` before returning.
+ * Errors: PFSM_EINVAL, PFSM_ENOMEM, PFSM_EHIP.                            */
+int pfsm_load_nfa(pfsm_t **out, const pfsm_nfa_desc *d, void *hip_stream);
+
+/* Add an expression to a loaded NFA handle without rebuilding it
+ * (Section III.A: expressions can be added or removed efficiently;
+ * Section IV: with zero downtime).  The pattern's automaton is put together
+ * with the handle's through an ancillary initial state and an epsilon edge
+ * (Section III.A).  Its labels must not occur in the handle.  Scans issued
+ * before the call keep the old automaton; scans issued after it (on any
+ * stream) see the new one.
+ * Errors: PFSM_EINVAL, PFSM_EEXIST (label already present), PFSM_ENOSYS
+ * (DFA handle: its table is monolithic), PFSM_ENOMEM, PFSM_EHIP.          */
+int pfsm_add_pattern(pfsm_t *h, const pfsm_nfa_desc *pattern, void *hip_stream);
+
+/* Remove an expression: after the call no match with `label` is reported.
+ * Patterns added with pfsm_add_pattern are cut off the ancillary initial
+ * state; otherwise the label is disabled in the label table.  Same snapshot
+ * semantics as pfsm_add_pattern.
+ * Errors: PFSM_ENOENT (label not present), PFSM_ENOMEM, PFSM_EHIP.        */
+int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream);
+
+/* Scan n bytes of device memory and report every match (Section III.B).
+ *   d_input    device pointer to n bytes (any alignment); n in [0, 2^31).
+ *   d_out      device array of `cap` pfsm_match_t, written in ascending
+ *              (start, end, label) order.
+ *   n_matches  host pointer, receives the total number of matches.
+ * Returns PFSM_EOVERFLOW when the total exceeds cap: *n_matches is still
+ * the exact total, d_out holds the first cap matches; retry with a larger
+ * buffer.  Synchronises `hip_stream` (the only device-to-host crossing).  */
+int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
+              int64_t *n_matches, void *hip_stream);
+
+/* pfsm_scan without the synchronisation: the total is written to the device
+ * int64 `d_n_matches` in stream order, and only the first `cap` matches are
+ * stored.  The caller compares *d_n_matches with cap once the stream has
+ * reached it.  Errors are argument errors only (PFSM_EINVAL, PFSM_ENOMEM,
+ * PFSM_EHIP).                                                             */
+int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
+                    int64_t cap, int64_t *d_n_matches, void *hip_stream);
+
+/* Scan many byte streams, each against one of several handles, in one pass.
+ *   hs                  host array of n_automata handles.
+ *   d_data              device bytes of all streams, concatenated.
+ *   d_stream_off        device int64 [n_streams + 1]: stream i is
+ *                       d_data[off[i], off[i+1]); each shorter than 2^31.
+ *   d_stream_automaton  device int32 [n_streams]: handle index per stream.
+ *   d_out, cap          device output, grouped by stream in stream order,
+ *                       each group in ascending (start, end, label) order;
+ *                       positions are relative to the stream's first byte.
+ *   d_match_off         device int64 [n_streams + 1]: group offsets.
+ *   n_matches           host pointer, receives the grand total.
+ * PFSM_EOVERFLOW as for pfsm_scan.  Synchronises `hip_stream`.           */
+int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data,
+                    const int64_t *d_stream_off, const int32_t *d_stream_automaton,
+                    int32_t n_streams, pfsm_match_t *d_out, int64_t cap, int64_t *d_match_off,
+                    int64_t *n_matches, void *hip_stream);
+
+/* Work counters of the most recent completed scan of `h` on `hip_stream`.
+ * Synchronises the stream.  Errors: PFSM_EINVAL, PFSM_ENOENT (no scan yet),
+ * PFSM_EHIP.                                                              */
+int pfsm_last_stats(pfsm_t *h, pfsm_stats *out, void *hip_stream);
+
+/* Release a handle and every device buffer it owns.  Waits for the device
+ * work that uses them.  NULL is ignored.                                   */
+void pfsm_free(pfsm_t *h);
+
+/* Static description of an error code. */
+const char *pfsm_strerror(int code);
+
+/* Description of the calling thread's most recent failure ("" if none). */
+const char *pfsm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFSM_H */

@@ -1,0 +1,260 @@
+"""Python binding of libpfsm (include/pfsm.h): an all-matches Parallel Finite
+State Machine scanner for MI355X (gfx950).
+
+The binding only marshals arguments: descriptors are passed as numpy arrays
+(any object with the descriptor's attribute names works, e.g. the ``DFA`` and
+``NFA`` dataclasses of the ``workloads`` package), device buffers as torch
+tensors, streams as ``torch.cuda.Stream`` (default: the current stream).
+Every step of a scan runs in the library's HIP kernels; when libpfsm.so is
+missing, loading fails loudly -- there is no fallback.
+
+Names follow the C ABI: ``pfsm_load_dfa``, ``pfsm_load_nfa``,
+``pfsm_add_pattern``, ``pfsm_remove_pattern``, ``pfsm_scan``,
+``pfsm_scan_async``, ``pfsm_scan_batch``, ``pfsm_last_stats``, ``pfsm_free``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpfsm.so")
+
+PFSM_OK = 0
+PFSM_EINVAL = -1
+PFSM_ENOMEM = -2
+PFSM_EOVERFLOW = -3
+PFSM_EHIP = -4
+PFSM_ENOENT = -5
+PFSM_EEXIST = -6
+PFSM_ENOSYS = -7
+
+# Exported symbols of libpfsm.so, as declared in include/pfsm.h.
+EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pattern", "pfsm_scan",
+           "pfsm_scan_async", "pfsm_scan_batch", "pfsm_last_stats", "pfsm_free", "pfsm_strerror",
+           "pfsm_last_error")
+
+
+class PfsmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class _DfaDesc(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int32), ("n_symbols", ctypes.c_int32), ("q0", ctypes.c_int32),
+                ("byte_to_symbol", ctypes.c_void_p), ("delta", ctypes.c_void_p),
+                ("final_off", ctypes.c_void_p), ("final_labels", ctypes.c_void_p)]
+
+
+class _NfaDesc(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int32), ("q0", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("edge_class", ctypes.c_void_p),
+                ("edge_dst", ctypes.c_void_p), ("class_bits", ctypes.c_void_p),
+                ("final_off", ctypes.c_void_p), ("final_labels", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("transitions", ctypes.c_int64), ("activations", ctypes.c_int64),
+                ("matches", ctypes.c_int64), ("long_walks", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpfsm.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpfsm.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "pfsm_load_dfa": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(_DfaDesc), vp]),
+        "pfsm_load_nfa": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(_NfaDesc), vp]),
+        "pfsm_add_pattern": (ctypes.c_int, [vp, ctypes.POINTER(_NfaDesc), vp]),
+        "pfsm_remove_pattern": (ctypes.c_int, [vp, i32, vp]),
+        "pfsm_scan": (ctypes.c_int, [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp]),
+        "pfsm_scan_async": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, vp]),
+        "pfsm_scan_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, i32, vp, i64, vp,
+                                           ctypes.POINTER(i64), vp]),
+        "pfsm_last_stats": (ctypes.c_int, [vp, ctypes.POINTER(_Stats), vp]),
+        "pfsm_free": (None, [vp]),
+        "pfsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "pfsm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != PFSM_OK:
+        lib = load_library()
+        raise PfsmError(rc, lib.pfsm_last_error().decode() or lib.pfsm_strerror(rc).decode())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _arr(a, dt, keep):
+    a = np.ascontiguousarray(a, dtype=dt)
+    keep.append(a)
+    return a.ctypes.data
+
+
+def _dfa_desc(d, keep) -> _DfaDesc:
+    b2s = None if d.byte_to_symbol is None else _arr(d.byte_to_symbol, np.int16, keep)
+    return _DfaDesc(int(d.n_states), int(d.n_symbols), int(d.q0), b2s, _arr(d.delta, np.int32, keep),
+                    _arr(d.final_off, np.int32, keep), _arr(d.final_labels, np.int32, keep))
+
+
+def _nfa_desc(a, keep) -> _NfaDesc:
+    return _NfaDesc(int(a.n_states), int(a.q0), int(a.n_classes), _arr(a.row_ptr, np.int32, keep),
+                    _arr(a.edge_class, np.int32, keep), _arr(a.edge_dst, np.int32, keep),
+                    _arr(a.class_bits, np.uint32, keep), _arr(a.final_off, np.int32, keep),
+                    _arr(a.final_labels, np.int32, keep))
+
+
+class Pfsm:
+    """A loaded automaton (owns the C handle)."""
+
+    def __init__(self, ptr: int, kind: str):
+        self._ptr = ptr
+        self.kind = kind
+
+    @property
+    def ptr(self) -> int:
+        if not self._ptr:
+            raise PfsmError(PFSM_EINVAL, "handle already freed")
+        return self._ptr
+
+    def free(self):
+        if self._ptr:
+            load_library().pfsm_free(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pfsm_load_dfa(dfa, stream=None) -> Pfsm:
+    lib = load_library()
+    keep = []
+    desc = _dfa_desc(dfa, keep)
+    h = ctypes.c_void_p()
+    _check(lib.pfsm_load_dfa(ctypes.byref(h), ctypes.byref(desc), _stream_ptr(stream)))
+    return Pfsm(h.value, "dfa")
+
+
+def pfsm_load_nfa(nfa, stream=None) -> Pfsm:
+    lib = load_library()
+    keep = []
+    desc = _nfa_desc(nfa, keep)
+    h = ctypes.c_void_p()
+    _check(lib.pfsm_load_nfa(ctypes.byref(h), ctypes.byref(desc), _stream_ptr(stream)))
+    return Pfsm(h.value, "nfa")
+
+
+def pfsm_load(automaton, stream=None) -> Pfsm:
+    return (pfsm_load_dfa if automaton.kind == "dfa" else pfsm_load_nfa)(automaton, stream)
+
+
+def pfsm_add_pattern(h: Pfsm, pattern, stream=None) -> None:
+    keep = []
+    desc = _nfa_desc(pattern, keep)
+    _check(load_library().pfsm_add_pattern(h.ptr, ctypes.byref(desc), _stream_ptr(stream)))
+
+
+def pfsm_remove_pattern(h: Pfsm, label: int, stream=None) -> None:
+    _check(load_library().pfsm_remove_pattern(h.ptr, int(label), _stream_ptr(stream)))
+
+
+def _check_input(x):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.uint8 and x.dim() == 1):
+        raise PfsmError(PFSM_EINVAL, "input must be a 1-D uint8 CUDA tensor")
+    if not x.is_contiguous():
+        raise PfsmError(PFSM_EINVAL, "input must be contiguous")
+
+
+def _check_out(out):
+    import torch
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.int32
+            and out.dim() == 2 and out.shape[1] == 3 and out.is_contiguous()):
+        raise PfsmError(PFSM_EINVAL, "out must be a contiguous [cap, 3] int32 CUDA tensor")
+
+
+def pfsm_scan(h: Pfsm, x, out=None, stream=None, cap: Optional[int] = None) -> Tuple[int, "torch.Tensor"]:
+    """Scan device bytes ``x``; returns (n_matches, out[:n_matches]).
+
+    With ``out=None`` an output of ``cap`` rows (default: n/16 + 1024) is
+    allocated and grown once when the scan reports overflow.  With a given
+    ``out`` too small for the result, PfsmError(PFSM_EOVERFLOW) is raised.
+    """
+    import torch
+    _check_input(x)
+    lib = load_library()
+    st = _stream_ptr(stream)
+    auto = out is None
+    if auto:
+        cap = cap if cap is not None else x.numel() // 16 + 1024
+        out = torch.empty((cap, 3), dtype=torch.int32, device=x.device)
+    _check_out(out)
+    n = ctypes.c_int64()
+    rc = lib.pfsm_scan(h.ptr, x.data_ptr(), x.numel(), out.data_ptr(), out.shape[0], ctypes.byref(n), st)
+    if rc == PFSM_EOVERFLOW and auto:
+        out = torch.empty((n.value, 3), dtype=torch.int32, device=x.device)
+        rc = lib.pfsm_scan(h.ptr, x.data_ptr(), x.numel(), out.data_ptr(), out.shape[0], ctypes.byref(n), st)
+    _check(rc)
+    return n.value, out[:n.value]
+
+
+def pfsm_scan_async(h: Pfsm, x, out, d_n_matches, stream=None) -> None:
+    """Enqueue a scan; the total goes to the int64 CUDA tensor ``d_n_matches``."""
+    import torch
+    _check_input(x)
+    _check_out(out)
+    if not (isinstance(d_n_matches, torch.Tensor) and d_n_matches.is_cuda and d_n_matches.dtype == torch.int64):
+        raise PfsmError(PFSM_EINVAL, "d_n_matches must be an int64 CUDA tensor")
+    _check(load_library().pfsm_scan_async(h.ptr, x.data_ptr(), x.numel(), out.data_ptr(), out.shape[0],
+                                          d_n_matches.data_ptr(), _stream_ptr(stream)))
+
+
+def pfsm_scan_batch(handles, data, stream_off, stream_automaton, out, match_off, stream=None) -> int:
+    """Scan concatenated streams; returns the grand total (see include/pfsm.h)."""
+    lib = load_library()
+    arr = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
+    n = ctypes.c_int64()
+    _check(lib.pfsm_scan_batch(arr, len(handles), data.data_ptr(), stream_off.data_ptr(),
+                               stream_automaton.data_ptr(), stream_automaton.numel(), out.data_ptr(),
+                               out.shape[0], match_off.data_ptr(), ctypes.byref(n), _stream_ptr(stream)))
+    return n.value
+
+
+def pfsm_last_stats(h: Pfsm, stream=None) -> dict:
+    s = _Stats()
+    _check(load_library().pfsm_last_stats(h.ptr, ctypes.byref(s), _stream_ptr(stream)))
+    return {"transitions": s.transitions, "activations": s.activations, "matches": s.matches,
+            "long_walks": s.long_walks}
+
+
+def pfsm_free(h: Pfsm) -> None:
+    h.free()

@@ -1,0 +1,27 @@
+// NFA side of the host library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+
+#include "pfsm.h"
+#include "pfsm_dev.h"
+
+namespace pfsmk {
+
+struct NfaHost;
+struct NfaDeleter {
+    void operator()(NfaHost *p) const;
+};
+using NfaPtr = std::unique_ptr<NfaHost, NfaDeleter>;
+
+int nfa_load(const pfsm_nfa_desc *d, hipStream_t s, NfaPtr *out, std::string *err);
+int nfa_add_pattern(NfaHost *h, const pfsm_nfa_desc *p, hipStream_t s, std::string *err);
+int nfa_remove_pattern(NfaHost *h, int32_t label, hipStream_t s, std::string *err);
+int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap, int64_t *d_total,
+                   hipStream_t s, std::string *err);
+int nfa_last_stats(NfaHost *h, hipStream_t s, long long v[4], std::string *err);
+
+}  // namespace pfsmk
