@@ -1,0 +1,167 @@
+"""Throughput of the all-matches PFSM scan on one MI355X.
+
+A step is one full scan (every start position, every match written in
+(start, end, label) order) of one 16 MiB input against a resident 256-state
+byte DFA: the random-DFA workload with planted accepting walks.  Inputs are
+resident in HBM before timing starts and rotate through 64 distinct copies
+(1 GiB), so that the 256 MB Infinity Cache cannot serve them.
+
+Prints one JSON line with GB/s (value), transitions/s, the single-scan
+latency distribution of the synchronous call, the roofline position of the
+scan kernel and the CPU oracle's throughput on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+MATCH_BYTES = 12       # one (start, end, label) int32 triple
+ROTATE_BYTES = 1 << 30
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--latency-iters", type=int, default=2000)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, seconds: float):
+    """The oracle as it is, on the host cores, over repeated passes of the
+    same 16 MiB input until `seconds` of wall time have been spent."""
+    import oracle
+    threads = oracle.default_threads()
+    oracle.scan(wl.automaton, wl.data[:1 << 16], threads=threads)  # load the library
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.scan(wl.automaton, wl.data, threads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds and reps >= 1:
+            break
+    return {"value": round(reps * wl.data.size / el / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} full passes over the 16 MiB input ({reps * wl.data.size} bytes, "
+                      f"{el:.1f} s wall)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the scan shards by input segment; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_1110_1716_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = W.cfg2()
+    n = wl.data.size
+    h = P.pfsm_load(wl.automaton)
+
+    host = torch.from_numpy(wl.data.copy())
+    n_copies = max(1, ROTATE_BYTES // n)
+    xs = [host.to(dev) for _ in range(n_copies)]
+    cap = n // 8 + 4096
+    out = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+    counts = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # reference count and work counters of one scan (from the kernel's own counters)
+    n_ref, _ = P.pfsm_scan(h, xs[0], out=out)
+    stats = P.pfsm_last_stats(h)
+    transitions = stats["transitions"]
+
+    for i in range(args.warmup):
+        P.pfsm_scan_async(h, xs[i % n_copies], out, counts[i:i + 1])
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for i in range(args.steps):
+        k = args.warmup + i
+        ev[i][0].record(stream)
+        P.pfsm_scan_async(h, xs[k % n_copies], out, counts[k:k + 1])
+        ev[i][1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    got = counts.cpu().numpy()
+    if not np.all(got == n_ref):
+        raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
+
+    ms_per_step = total_ms / args.steps
+    gbs = n * args.steps / (total_ms / 1e3) / 1e9
+    tps = transitions * args.steps / (total_ms / 1e3)
+
+    # single-scan latency of the synchronous call (launch + count read-back)
+    lat = []
+    for i in range(args.latency_iters):
+        t0 = time.perf_counter()
+        P.pfsm_scan(h, xs[i % n_copies], out=out)
+        lat.append(time.perf_counter() - t0)
+    lat_us = np.array(lat) * 1e6
+
+    kern_avg_s = float(kern_ms.mean()) / 1e3
+    alg_bytes = n + MATCH_BYTES * n_ref
+    achieved = alg_bytes / kern_avg_s / 1e9
+
+    res = {
+        "metric": "input GB/s and transitions/s per MI355X (batched vs plain); p50/p99 scan latency",
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_bytes": n, "seed": wl.seed, "n_states": 256,
+                   "n_symbols": 256, "finals": 16, "matches_per_scan": int(n_ref),
+                   "resident_input_copies": n_copies},
+        "transitions_per_s": round(tps, 1),
+        "transitions_per_scan": int(transitions),
+        "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
+                       "p99": round(float(np.percentile(lat_us, 99)), 2),
+                       "iters": args.latency_iters, "call": "pfsm_scan (synchronous)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "dfa_scan_kernel", "kernel_avg_us": round(kern_avg_s * 1e6, 3),
+                     "alg_bytes_per_launch": int(alg_bytes)},
+        "wall_s_timed": round(wall, 4),
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    h.free()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,287 +1,490 @@
 // All-matches DFA scan for gfx950 (Section III.B with a deterministic
-// transition function; Section III.C's DFA case).
+// transition function; the DFA case of Section III.C).
 //
-// One workgroup owns the start positions of one window of W = 256*B bytes
-// (lazy data partitioning, Section III.D.2: a window owns its starts and its
-// walks read past its end until they die).  Per window:
-//   1. stage x[base, base + W + kOverlap) from HBM into LDS, 16 B per load;
-//   2. first step of every start (the tagged reinitialisation of q0 followed
-//      by one symbol, Section III.B steps 1-4) from the q0 row cached in LDS,
-//      indexed by byte;
-//   3. survivors go to an LDS queue (ballot + prefix-sum compaction) and
-//      advance kSteps symbols per round through the unmodified table (L2),
-//      re-packed after every round, until the queue is empty;
-//   4. every final state entered emits (start, end, label) into an LDS
-//      buffer (Section III.B reporting rule);
-//   5. the window's count goes through a decoupled look-back to get its
-//      global offset; each buffered match is placed by its rank in
-//      (start, end, label) order.  A window with more matches than the buffer
-//      holds re-walks its starts 256 at a time, counting then writing.
+// Persistent cooperative grid of 1024-thread workgroups (16 wave64, one per
+// compute unit when the table is resident in LDS).  Workgroup b owns the
+// start positions of one contiguous segment per round (lazy data
+// partitioning, Section III.D.2: a segment owns its starts, its walks read
+// past its end until they die).  The segment is processed in 16 KiB windows:
+//   1. the window is staged from HBM into LDS with 16-byte loads issued two
+//      windows ahead;
+//   2. every start takes its first symbol through the row of q0 cached in LDS
+//      by byte (Section III.B steps 1-4 for the fresh tag), 16 independent
+//      lookups per thread; the live ones take their second symbol through
+//      the table (resident in LDS, or the LDS copies of q0's successor rows);
+//   3. walks still live go to a wave-private LDS queue (ballot + prefix
+//      popcount) and advance in rounds of up to 16 symbols per walk, the
+//      symbols coming from one 16-byte chunk (LDS inside the window, L2
+//      outside it); walks left at the end of a window carry over;
+//   4. every final state entered adds (start, end, label) to an LDS buffer
+//      under the key (start - segment start, k), k = the instance's match
+//      count so far, which orders (end, label) within a start (Section III.B
+//      reporting rule).
+// At the end of a round each workgroup publishes its match count in its own
+// epoch-tagged slot and sums its peers' slots (no shared counters), then
+// writes every buffered match at its rank.  A segment whose matches do not
+// fit the buffer is re-walked 1024 starts at a time: count, scan, write.
 #include "scan_common.h"
 
 namespace pfsmk {
 
 namespace {
 
-constexpr int kQCap = 512;   // LDS queue entries per buffer (double-buffered)
-constexpr int kMCap = 512;   // LDS match buffer entries
-constexpr int kSteps = 4;    // symbols advanced per queue round
+constexpr int NT = kDfaThreads;
+constexpr int W = kDfaWindow;
+constexpr int QW = kDfaQueue;
+constexpr int QK = QW / 64;
+constexpr int MC = kDfaMatchCap;
 
 struct QEnt {
-    int32_t start, state, pos, pad;
-};
-struct MEnt {
-    int32_t start, end, label, pad;
+    int32_t start, state, pos, k;
 };
 
-template <typename TT, bool kId>
-struct Dfa {
+template <int ENC, bool kId>
+struct DfaCtx {
     const DfaArgs &a;
     const uint8_t *xs;
     const int32_t *first_s;
+    const int16_t *slot_s;
     const int16_t *b2s_s;
     const uint8_t *flags_s;
-    int64_t base;
+    const int32_t *laboff_s;
+    const int32_t *lab_s;
+    const uint8_t *tab_s;
+    uint32_t *mkey;
+    int32_t *mend;
+    int32_t *mlab;
+    int *mn;
+    int *ovf;
+    int64_t wbase;
     int staged;
-    bool flags_lds;
+    int64_t seg_lo;
+    int32_t n32;
+    long long T = 0, X = 0, L = 0, M = 0;
 
-    __device__ __forceinline__ int byte_at(int32_t pos) const {
-        const int64_t r = (int64_t)pos - base;
-        return r < staged ? (int)xs[r] : (int)a.x[pos];
+    static constexpr bool kResident = ENC == kEnc8 || ENC == kEnc8D || ENC == kEnc16;
+
+    __device__ __forceinline__ uint8_t flag(int s) const {
+        if constexpr (kResident) return flags_s[s];
+        else return a.flags[s];
     }
-    __device__ __forceinline__ uint8_t flag(int s) const { return flags_lds ? flags_s[s] : a.flags[s]; }
-    // One symbol from state s: the target, or -1 when the instance ends.
-    __device__ __forceinline__ int step(int s, int byte) const {
-        const int sym = kId ? byte : (int)b2s_s[byte];
-        if (sym < 0) return -1;
-        const TT *t = reinterpret_cast<const TT *>(a.tbl);
-        const int nx = (int)t[(int64_t)s * a.n_symbols + sym];
-        if (nx < 0) return -1;
-        return (flag(nx) & kLive) ? nx : -1;
+    __device__ __forceinline__ int sym(int byte) const { return kId ? byte : (int)b2s_s[byte]; }
+    // delta(s, sy) as given: a state or -1.
+    __device__ __forceinline__ int tab(int s, int sy) const {
+        const int64_t i = (int64_t)s * a.n_symbols + sy;
+        if constexpr (ENC == kEnc8) {
+            const int v = tab_s[i];
+            return v == 255 ? -1 : v;
+        } else if constexpr (ENC == kEnc8D) {
+            const int ns = a.n_states * a.n_symbols;
+            const uint32_t *dead = reinterpret_cast<const uint32_t *>(tab_s + ((ns + 3) & ~3));
+            return (dead[i >> 5] >> (i & 31)) & 1u ? -1 : (int)tab_s[i];
+        } else if constexpr (ENC == kEnc16) {
+            return reinterpret_cast<const int16_t *>(tab_s)[i];
+        } else if constexpr (ENC == kCold16) {
+            return reinterpret_cast<const int16_t *>(a.tbl)[i];
+        } else {
+            return reinterpret_cast<const int32_t *>(a.tbl)[i];
+        }
+    }
+    // Second symbol of a walk whose first step read byte b0 and reached s1.
+    __device__ __forceinline__ int tab2(int b0, int s1, int sy) const {
+        if constexpr (kResident) {
+            return tab(s1, sy);
+        } else {
+            const int slot = slot_s[b0];
+            if (slot < 0) return tab(s1, sy);
+            if constexpr (ENC == kCold16) return reinterpret_cast<const int16_t *>(tab_s)[slot * a.n_symbols + sy];
+            else return reinterpret_cast<const int32_t *>(tab_s)[slot * a.n_symbols + sy];
+        }
+    }
+    __device__ __forceinline__ int live(int t) const { return (t >= 0 && (flag(t) & kLive)) ? t : -1; }
+    __device__ __forceinline__ int lab_lo(int s) const {
+        if constexpr (kResident) return laboff_s[s];
+        else return a.lab_off[s];
+    }
+    __device__ __forceinline__ int lab_at(int l) const {
+        if constexpr (kResident) return lab_s[l];
+        else return a.lab[l];
+    }
+    // Report every label of s for the instance started at `start`.
+    __device__ __forceinline__ void emit(int32_t start, int32_t end, int s, int32_t &k) {
+        const int lo = lab_lo(s), hi = lab_lo(s + 1);
+        M += hi - lo;
+        for (int l = lo; l < hi; ++l, ++k) {
+            if (*ovf) continue;
+            const int slot = atomicAdd(mn, 1);
+            if (slot < MC) {
+                mkey[slot] = ((uint32_t)(start - seg_lo) << 16) | (uint32_t)(k & 0xffff);
+                mend[slot] = end;
+                mlab[slot] = lab_at(l);
+            } else {
+                *ovf = 1;
+            }
+        }
+    }
+    // The 16-byte chunk holding position p (p is a multiple of 16).
+    __device__ __forceinline__ uint4 chunk(int64_t p) {
+        const int64_t r = p - wbase;
+        if (r >= 0 && r + 16 <= staged) return *reinterpret_cast<const uint4 *>(xs + r);
+        ++L;
+        return load_granule(a.x, p);
     }
 };
 
-template <int B, typename TT, bool kId>
-__global__ __launch_bounds__(kBlock) void dfa_scan_kernel(DfaArgs a) {
-    constexpr int W = kBlock * B;
-    constexpr int XS = W + kOverlap;
-    __shared__ __align__(16) uint8_t xs[XS];
-    __shared__ int32_t first_s[256];
-    __shared__ int16_t b2s_s[256];
-    __shared__ uint8_t flags_s[kFlagsLds];
-    __shared__ QEnt q[2][kQCap];
-    __shared__ MEnt mb[kMCap];
-    __shared__ int qn[2];
-    __shared__ int mn;
-    __shared__ int ovf;
-    __shared__ int last_flag;
-    __shared__ unsigned wid_s;
-    __shared__ long long red[kBlock / 64];
-    __shared__ long long excl_s;
+// One round: every walk in this wave's queue advances through the rest of
+// the 16-byte chunk holding its next position (up to 16 symbols); walks that
+// end are dropped and the queue is re-packed.
+template <int ENC, bool kId>
+__device__ __forceinline__ void drain_round(DfaCtx<ENC, kId> &c, QEnt *q, int &qcount) {
+    const int lane = lane_id();
+    QEnt e[QK];
+    bool alive[QK];
+    uint4 ch[QK];
+    int steps[QK];
+#pragma unroll
+    for (int j = 0; j < QK; ++j) {
+        const int idx = lane + 64 * j;
+        alive[j] = idx < qcount;
+        e[j] = alive[j] ? q[idx] : QEnt{0, 0, 0, 0};
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < QK; ++j) {
+        const int64_t c0 = (int64_t)(e[j].pos & ~15);
+        ch[j] = alive[j] ? c.chunk(c0) : make_uint4(0, 0, 0, 0);
+        const int64_t end = c0 + 16 < c.a.n ? c0 + 16 : c.a.n;
+        steps[j] = (int)(end - e[j].pos);  // symbols left in this chunk
+    }
+    // t[j]: target of the walk's next symbol, looked up one step ahead so
+    // that the flag read of a state overlaps the table read of its successor.
+    int t[QK];
+#pragma unroll
+    for (int j = 0; j < QK; ++j) {
+        const int sy = c.sym(byte_of(ch[j], e[j].pos & 15));
+        t[j] = (alive[j] && sy >= 0) ? c.tab(e[j].state, sy) : -1;
+    }
+#pragma unroll 1
+    for (int st = 0; st < 16; ++st) {
+        bool more = false;
+#pragma unroll
+        for (int j = 0; j < QK; ++j) {
+            if (alive[j] && st < steps[j]) {
+                ++c.T;
+                const int cur = t[j];
+                if (cur < 0) {
+                    alive[j] = false;
+                } else {
+                    const uint8_t f = c.flag(cur);
+                    int nxt = -1;
+                    if (st + 1 < steps[j]) {
+                        const int sy = c.sym(byte_of(ch[j], (e[j].pos + 1) & 15));
+                        if (sy >= 0) nxt = c.tab(cur, sy);
+                    }
+                    if (!(f & kLive)) {
+                        alive[j] = false;
+                    } else {
+                        ++c.X;
+                        if (f & kFinal) c.emit(e[j].start, e[j].pos, cur, e[j].k);
+                        e[j].state = cur;
+                        ++e[j].pos;
+                        t[j] = nxt;
+                        more |= st + 1 < steps[j];
+                    }
+                }
+            }
+        }
+        if (!__any(more)) break;
+    }
+    int nc = 0;
+#pragma unroll
+    for (int j = 0; j < QK; ++j) {
+        const bool keep = alive[j] && e[j].pos < c.n32;
+        const int slot = wave_push_slot(nc, keep);
+        if (keep) q[slot] = e[j];
+    }
+    __builtin_amdgcn_wave_barrier();
+    qcount = nc;
+}
+
+// The full walk of one start reading the input through the cache hierarchy;
+// counts its matches, or writes them from output index `at` when write.
+template <int ENC, bool kId>
+__device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32_t i, bool write, long long at) {
+    const DfaArgs &a = c.a;
+    long long cnt = 0;
+    int s = c.first_s[a.x[i]];
+    int32_t pos = i;
+    while (s >= 0) {
+        for (int l = c.lab_lo(s); l < c.lab_lo(s + 1); ++l, ++cnt) {
+            if (write && at + cnt < a.cap) {
+                MatchOut *p = &a.out[at + cnt];
+                p->start = i;
+                p->end = pos;
+                p->label = c.lab_at(l);
+            }
+        }
+        if (++pos >= c.n32) break;
+        const int sy = c.sym(a.x[pos]);
+        s = sy < 0 ? -1 : c.live(c.tab(s, sy));
+    }
+    return cnt;
+}
+
+template <int ENC, bool kId>
+__global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint8_t *xs = lds;
+    int32_t *first_s = reinterpret_cast<int32_t *>(lds + W);
+    int16_t *slot_s = reinterpret_cast<int16_t *>(first_s + 256);
+    int16_t *b2s_s = slot_s + 256;
+    uint8_t *flags_s = lds + a.off_flags;
+    int32_t *laboff_s = reinterpret_cast<int32_t *>(lds + a.off_laboff);
+    int32_t *lab_s = reinterpret_cast<int32_t *>(lds + a.off_lab);
+    uint8_t *tab_s = lds + a.off_tab;
+    QEnt *qall = reinterpret_cast<QEnt *>(lds + a.off_q);
+    uint32_t *mkey = reinterpret_cast<uint32_t *>(lds + a.off_m);
+    int32_t *mend = reinterpret_cast<int32_t *>(mkey + MC);
+    int32_t *mlab = mend + MC;
+    __shared__ int mn, ovf;
+    __shared__ long long red[NT / 64];
+    __shared__ long long red4[4 * (NT / 64)];
+    __shared__ unsigned epoch_s;
 
     const int tid = threadIdx.x;
+    const int wv = tid >> 6;
+    const int b = blockIdx.x;
+    const int32_t n32 = (int32_t)a.n;
+
+    // Issue the first two windows' loads before anything else.
+    auto seg_of = [&](int r, int64_t &lo, int64_t &hi) __attribute__((always_inline)) {
+        lo = ((int64_t)r * a.n_blocks + b) * a.seg;
+        hi = lo + a.seg < a.n ? lo + a.seg : a.n;
+    };
+    int64_t seg_lo, seg_hi;
+    seg_of(0, seg_lo, seg_hi);
+    // Window stream over the rounds: (round, window base) in order.
+    int pr = 0;
+    int64_t pw = seg_lo, plo = seg_lo, phi = seg_hi;
+    auto next_window = [&](int64_t &wb, bool &ok) __attribute__((always_inline)) {
+        // advance (pr, pw) to the next window that has starts
+        while (pr < a.n_rounds) {
+            if (pw < phi) {
+                wb = pw;
+                pw += W;
+                ok = true;
+                return;
+            }
+            ++pr;
+            if (pr < a.n_rounds) {
+                seg_of(pr, plo, phi);
+                pw = plo;
+            }
+        }
+        ok = false;
+    };
+    auto fetch = [&](int64_t wb, uint4 &v) __attribute__((always_inline)) {
+        const int64_t p = wb + 16 * tid;
+        v = p < a.n ? load_granule(a.x, p) : make_uint4(0, 0, 0, 0);
+    };
+    // Two prefetch buffers used alternately: buffer p holds the window
+    // after next while the other one's window is being processed.
+    int64_t pwb[2] = {0, 0};
+    bool pok[2] = {false, false};
+    uint4 pv[2];
+    next_window(pwb[0], pok[0]);
+    if (pok[0]) fetch(pwb[0], pv[0]);
+    next_window(pwb[1], pok[1]);
+    if (pok[1]) fetch(pwb[1], pv[1]);
+
+    // Tables into LDS.
+    if (tid < 256) {
+        first_s[tid] = a.first[tid];
+        slot_s[tid] = a.first_slot[tid];
+        b2s_s[tid] = a.b2s[tid];
+    }
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.res);
+        uint4 *dst = reinterpret_cast<uint4 *>(tab_s);
+        for (int i = tid; i < (a.res_bytes >> 4); i += NT) dst[i] = src[i];
+    }
+    if (DfaCtx<ENC, kId>::kResident) {
+        for (int i = tid; i < a.n_states; i += NT) flags_s[i] = a.flags[i];
+        for (int i = tid; i <= a.n_states; i += NT) laboff_s[i] = a.lab_off[i];
+        const int nnz = a.lab_off[a.n_states];
+        for (int i = tid; i < nnz; i += NT) lab_s[i] = a.lab[i];
+    }
     if (tid == 0) {
-        wid_s = atomicAdd(&a.ctl->ticket, 1u);
-        qn[0] = qn[1] = 0;
         mn = 0;
         ovf = 0;
+        epoch_s = first_epoch(a.slots, b);
     }
-    first_s[tid] = a.first[tid];
-    if (!kId) b2s_s[tid] = a.b2s[tid];
-    const bool flags_lds = a.n_states <= kFlagsLds;
-    if (flags_lds)
-        for (int i = tid; i < a.n_states; i += kBlock) flags_s[i] = a.flags[i];
     __syncthreads();
+    const unsigned epoch0 = epoch_s;
 
-    const long long w = wid_s;
-    const int64_t base = w * (int64_t)W;
-    const int64_t lim = a.n - base;  // starts owned: [base, base + min(W, lim))
-    const int staged = (int)(lim < XS ? lim : XS);
-    stage_bytes(xs, a.x + base, staged);
-    __syncthreads();
+    DfaCtx<ENC, kId> c{a, xs, first_s, slot_s, b2s_s, flags_s, laboff_s, lab_s, tab_s, mkey,
+                       mend, mlab, &mn, &ovf, 0, 0, 0, n32};
+    QEnt *q = qall + wv * QW;
+    int qcount = 0;
+    long long base_out = 0;
 
-    Dfa<TT, kId> d{a, xs, first_s, b2s_s, flags_s, base, staged, flags_lds};
-    const int32_t n32 = (int32_t)a.n;
-    long long tT = 0, tX = 0, tM = 0, tL = 0;
+    // Process the window held in prefetch buffer p, then refill p with the
+    // window two ahead.  Called with p = 0, 1, 0, 1, ... (static indices).
+    auto run_window = [&](const int p) __attribute__((always_inline)) {
+        const int64_t wbase = pwb[p];
+        const int64_t wend = wbase + W < seg_hi ? wbase + W : seg_hi;
+        const int64_t rest = a.n - wbase;
+        const int staged = (int)(rest < W ? rest : W);
+        __syncthreads();  // every wave is done with the previous window's bytes
+        *reinterpret_cast<uint4 *>(xs + 16 * tid) = pv[p];
+        const uint4 mine = pv[p];
+        next_window(pwb[p], pok[p]);
+        if (pok[p]) fetch(pwb[p], pv[p]);
+        __syncthreads();
+        c.wbase = wbase;
+        c.staged = staged;
 
-    auto emit = [&](int32_t start, int32_t end, int s) {
-        const int lo = a.lab_off[s], hi = a.lab_off[s + 1];
-        tM += hi - lo;
-        for (int l = lo; l < hi; ++l) {
-            if (ovf) break;
-            const int slot = atomicAdd(&mn, 1);
-            if (slot < kMCap) {
-                mb[slot] = MEnt{start, end, a.lab[l], 0};
-            } else {
-                ovf = 1;
-            }
-        }
-    };
-
-    int cur = 0;
-    // Advance every queued walk until the queue is empty.
-    // Each round: every thread reads the count, a barrier guarantees that
-    // before anyone pushes again, then survivors are re-packed into the other
-    // buffer.
-    auto drain = [&]() {
+        // First symbol of the 16 starts owned by this thread.
+        const int il0 = 16 * tid;
+        const int64_t i0 = wbase + il0;
+        const int64_t nv64 = wend - i0;
+        const int nvalid = nv64 <= 0 ? 0 : (nv64 >= 16 ? 16 : (int)nv64);
+        // byte after this thread's 16 (the next window's first byte for the
+        // last thread)
+        const int tail = (nvalid == 16 && i0 + 16 < a.n) ? (il0 + 16 < staged ? xs[il0 + 16] : a.x[i0 + 16]) : 0;
+        unsigned live_mask = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < nvalid && first_s[byte_of(mine, k)] >= 0) live_mask |= 1u << k;
+        c.T += nvalid;
+        c.X += __popc(live_mask);
+        // Second symbol of the live ones, one per lane per pass so the queue
+        // pushes stay wave-uniform.
         for (;;) {
-            __syncthreads();
-            const int cnt = qn[cur];
-            __syncthreads();
-            if (cnt == 0) break;
-            const int nxt = cur ^ 1;
-            if (tid == 0) qn[cur] = 0;
-            for (int e0 = 0; e0 < cnt; e0 += kBlock) {
-                const int e = e0 + tid;
-                bool alive = e < cnt;
-                QEnt en{0, 0, 0, 0};
-                if (alive) en = q[cur][e];
-#pragma unroll 1
-                for (int r = 0; r < kSteps && alive; ++r) {
-                    if (en.pos >= n32) { alive = false; break; }
-                    if ((int64_t)en.pos - base == staged) ++tL;
-                    const int b = d.byte_at(en.pos);
-                    ++tT;
-                    const int s2 = d.step(en.state, b);
-                    if (s2 < 0) { alive = false; break; }
-                    ++tX;
-                    if (d.flag(s2) & kFinal) emit(en.start, en.pos, s2);
-                    en.state = s2;
-                    ++en.pos;
-                }
-                if (alive && en.pos >= n32) alive = false;
-                const int slot = wave_reserve(&qn[nxt], alive);
-                if (alive) q[nxt][slot] = en;
-            }
-            cur = nxt;
-        }
-    };
-
-    // First step of every start: q0 (tag = position) consumes its byte.
-#pragma unroll 1
-    for (int j = 0; j < B; ++j) {
-        const int il = j * kBlock + tid;
-        bool push = false;
-        int s = -1;
-        if (il < lim) {
-            const int32_t i = (int32_t)(base + il);
-            s = first_s[xs[il]];
-            ++tT;
-            if (s >= 0) {
-                ++tX;
-                if (d.flag(s) & kFinal) emit(i, i, s);
-                push = i + 1 < n32;
-            }
-        }
-        const int slot = wave_reserve(&qn[cur], push);
-        if (push) q[cur][slot] = QEnt{(int32_t)(base + il), s, (int32_t)(base + il + 1), 0};
-        __syncthreads();
-        const int queued = qn[cur];
-        __syncthreads();
-        if (queued > kQCap - kBlock) drain();
-    }
-    drain();
-
-    // Window total, look-back, placement.
-    const long long wtot = block_sum(tM, red);
-    if (tid < 64) {
-        const long long ex = lookback(a.status, w, wtot);
-        if (tid == 0) {
-            excl_s = ex;
-            if (w == a.n_windows - 1) *a.total = ex + wtot;
-        }
-    }
-    __syncthreads();
-    const long long excl = excl_s;
-
-    if (!ovf) {
-        const int m = mn;
-        for (int e = tid; e < m; e += kBlock) {
-            const MEnt me = mb[e];
-            int rank = 0;
-            for (int k = 0; k < m; ++k) {
-                const MEnt o = mb[k];
-                rank += (o.start < me.start) ||
-                        (o.start == me.start && (o.end < me.end || (o.end == me.end && o.label < me.label)));
-            }
-            const long long at = excl + rank;
-            if (at < a.cap) {
-                MatchOut *p = &a.out[at];
-                p->start = me.start;
-                p->end = me.end;
-                p->label = me.label;
-            }
-        }
-    } else {
-        // Dense window: 256 starts at a time, thread order = start order.
-        long long run = excl;
-#pragma unroll 1
-        for (int c = 0; c < B; ++c) {
-            const int il = c * kBlock + tid;
-            const bool own = il < lim;
-            const int32_t i = (int32_t)(base + il);
-            long long cnt = 0;
-            if (own) {
-                int s = first_s[xs[il]];
-                int32_t pos = i;
-                while (s >= 0) {
-                    cnt += a.lab_off[s + 1] - a.lab_off[s];
-                    if (++pos >= n32) break;
-                    s = d.step(s, d.byte_at(pos));
-                }
-            }
-            long long ctot;
-            const long long ex = block_excl_scan(cnt, red, &ctot);
-            if (own && cnt) {
-                long long at = run + ex;
-                int s = first_s[xs[il]];
-                int32_t pos = i;
-                while (s >= 0) {
-                    for (int l = a.lab_off[s]; l < a.lab_off[s + 1]; ++l, ++at) {
-                        if (at < a.cap) {
-                            MatchOut *p = &a.out[at];
-                            p->start = i;
-                            p->end = pos;
-                            p->label = a.lab[l];
+            const bool more = __any(live_mask != 0);
+            if (!more) break;
+            bool push = false;
+            QEnt ent{0, 0, 0, 0};
+            if (live_mask) {
+                const int k = __ffs(live_mask) - 1;
+                live_mask &= live_mask - 1;
+                const int b0 = byte_of(mine, k);
+                const int b1 = k < 15 ? byte_of(mine, k + 1) : tail;
+                const int32_t i = (int32_t)(i0 + k);
+                const int s1 = first_s[b0];
+                int32_t km = 0;
+                if (c.flag(s1) & kFinal) c.emit(i, i, s1, km);
+                if (i + 1 < n32) {
+                    ++c.T;
+                    const int sy = c.sym(b1);
+                    const int s2 = sy < 0 ? -1 : c.live(c.tab2(b0, s1, sy));
+                    if (s2 >= 0) {
+                        ++c.X;
+                        if (c.flag(s2) & kFinal) c.emit(i, i + 1, s2, km);
+                        if (i + 2 < n32) {
+                            push = true;
+                            ent = QEnt{i, s2, i + 2, km};
                         }
                     }
-                    if (++pos >= n32) break;
-                    s = d.step(s, d.byte_at(pos));
                 }
             }
-            run += ctot;
+            const int slot = wave_push_slot(qcount, push);
+            if (push) q[slot] = ent;
+            while (qcount > QW - 64) drain_round(c, q, qcount);
+        }
+    };
+
+    for (int r = 0; r < a.n_rounds; ++r) {
+        seg_of(r, seg_lo, seg_hi);
+        c.seg_lo = seg_lo;
+        const long long m_before = c.M;
+        auto in_round = [&](int p) __attribute__((always_inline)) { return pok[p] && pwb[p] >= seg_lo && pwb[p] < seg_hi; };
+        for (;;) {
+            if (!in_round(0)) break;
+            run_window(0);
+            if (!in_round(1)) break;
+            run_window(1);
+        }
+        // The round's walks run to their end.
+        while (qcount > 0) drain_round(c, q, qcount);
+
+        // Offsets: this round's count, the peers' counts, placement.
+        const long long mine_m = block_sum<NT>(c.M - m_before, red);
+        long long round_total;
+        const long long excl =
+            grid_prefix<NT>(a.slots, a.n_blocks, b, (epoch0 + r) & kEpochMask, mine_m, red, &round_total);
+        const long long at0 = base_out + excl;
+        if (!ovf) {
+            const int m = mn;
+            if (tid < m) {
+                const uint32_t mk = mkey[tid];
+                int rank = 0;
+                int k = 0;
+                for (; k + 16 <= m; k += 16) {
+                    const uint4 k0 = *reinterpret_cast<const uint4 *>(mkey + k);
+                    const uint4 k1 = *reinterpret_cast<const uint4 *>(mkey + k + 4);
+                    const uint4 k2 = *reinterpret_cast<const uint4 *>(mkey + k + 8);
+                    const uint4 k3 = *reinterpret_cast<const uint4 *>(mkey + k + 12);
+                    rank += (k0.x < mk) + (k0.y < mk) + (k0.z < mk) + (k0.w < mk);
+                    rank += (k1.x < mk) + (k1.y < mk) + (k1.z < mk) + (k1.w < mk);
+                    rank += (k2.x < mk) + (k2.y < mk) + (k2.z < mk) + (k2.w < mk);
+                    rank += (k3.x < mk) + (k3.y < mk) + (k3.z < mk) + (k3.w < mk);
+                }
+                for (; k < m; ++k) rank += mkey[k] < mk;
+                const long long at = at0 + rank;
+                if (at < a.cap) {
+                    MatchOut *p = &a.out[at];
+                    p->start = (int32_t)(seg_lo + (mk >> 16));
+                    p->end = mend[tid];
+                    p->label = mlab[tid];
+                }
+            }
+        } else {
+            long long run = at0;
+            for (int64_t c0 = seg_lo; c0 < seg_hi; c0 += NT) {
+                const int64_t i = c0 + tid;
+                const bool own = i < seg_hi;
+                const long long cnt = own ? walk_start(c, (int32_t)i, false, 0) : 0;
+                long long ctot;
+                const long long ex = block_excl_scan<NT>(cnt, red, &ctot);
+                if (own && cnt) walk_start(c, (int32_t)i, true, run + ex);
+                run += ctot;
+            }
+        }
+        base_out += round_total;
+        __syncthreads();
+        if (tid == 0) {
+            mn = 0;
+            ovf = 0;
         }
     }
-
-    const long long bT = block_sum(tT, red);
-    const long long bX = block_sum(tX, red);
-    const long long bL = block_sum(tL, red);
-    finish_launch(a.ctl, a.status, a.n_windows, bT, bX, bL, wtot, &last_flag);
+    if (b == 0 && tid == 0) *a.total = base_out;
+    long long st4[4] = {c.T, c.X, c.L, c.M};
+    block_sum4<NT>(st4, red4);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.bstats[4 * b + k] = st4[k];
+    }
 }
 
 __global__ void write_zero_kernel(int64_t *p) { *p = 0; }
 
-template <int B, typename TT, bool kId>
-hipError_t launch_one(const DfaArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((dfa_scan_kernel<B, TT, kId>), dim3(a.n_windows), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-template <int B>
-hipError_t launch_b(const DfaArgs &a, bool id, bool t16, hipStream_t s) {
-    if (t16) return id ? launch_one<B, int16_t, true>(a, s) : launch_one<B, int16_t, false>(a, s);
-    return id ? launch_one<B, int32_t, true>(a, s) : launch_one<B, int32_t, false>(a, s);
+template <int ENC>
+const void *pick(bool id) {
+    return id ? reinterpret_cast<const void *>(&dfa_scan_kernel<ENC, true>)
+              : reinterpret_cast<const void *>(&dfa_scan_kernel<ENC, false>);
 }
 
 }  // namespace
 
-hipError_t launch_dfa_scan(const DfaArgs &a, int per_thread, bool identity_map, bool tbl16,
-                           hipStream_t stream) {
-    switch (per_thread) {
-    case 1: return launch_b<1>(a, identity_map, tbl16, stream);
-    case 4: return launch_b<4>(a, identity_map, tbl16, stream);
-    case 16: return launch_b<16>(a, identity_map, tbl16, stream);
-    default: return hipErrorInvalidValue;
+const void *dfa_kernel_fn(int enc, bool identity_map) {
+    switch (enc) {
+    case kEnc8: return pick<kEnc8>(identity_map);
+    case kEnc8D: return pick<kEnc8D>(identity_map);
+    case kEnc16: return pick<kEnc16>(identity_map);
+    case kCold16: return pick<kCold16>(identity_map);
+    case kCold32: return pick<kCold32>(identity_map);
+    default: return nullptr;
     }
 }
 

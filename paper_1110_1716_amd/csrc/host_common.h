@@ -1,0 +1,182 @@
+// Host-side helpers shared by the DFA and NFA halves of libpfsm: error
+// reporting, owned device buffers and per-stream scan workspaces.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pfsm.h"
+#include "pfsm_dev.h"
+
+namespace pfsmk {
+
+// Thread-local description of the most recent failure (pfsm_last_error).
+std::string &last_error();
+
+inline int fail(int code, const char *fmt, ...) {
+    char buf[640];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    last_error() = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return ::pfsmk::fail(e_ == hipErrorOutOfMemory ? PFSM_ENOMEM : PFSM_EHIP, "%s: %s (%s:%d)", \
+                                 #expr, hipGetErrorString(e_), __FILE__, __LINE__);              \
+    } while (0)
+
+// A device buffer owned by a handle.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        HIP_TRY(hipMalloc(&p, n));
+        bytes = n;
+        return PFSM_OK;
+    }
+    // Copies `count` elements; the caller synchronises `s` before `src` dies.
+    template <typename T>
+    int upload(const T *src, size_t count, hipStream_t s) {
+        int rc = alloc(count * sizeof(T));
+        if (rc) return rc;
+        if (count) HIP_TRY(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+        return PFSM_OK;
+    }
+    template <typename T>
+    T *as() const {
+        return static_cast<T *>(p);
+    }
+};
+
+// Scan scratch of one handle on one stream: the persistent grid's count
+// slots (zeroed once, epoch-tagged afterwards), per-workgroup work counters,
+// the device total and pinned host mirrors for reading them back.
+struct Workspace {
+    hipStream_t stream = nullptr;
+    int n_blocks = 0;
+    unsigned long long *slots = nullptr;  // [n_blocks]
+    long long *bstats = nullptr;          // [n_blocks * 4]
+    int64_t *d_total = nullptr;
+    int64_t *h_total = nullptr;           // pinned
+    long long *h_stats = nullptr;         // pinned [n_blocks * 4]
+    bool scanned = false;
+    uint8_t *stage = nullptr;             // aligned copy of a misaligned input
+    int64_t stage_cap = 0;
+    std::vector<void *> extra;            // kernel-specific scratch
+
+    ~Workspace() {
+        if (slots) (void)hipFree(slots);
+        if (bstats) (void)hipFree(bstats);
+        if (d_total) (void)hipFree(d_total);
+        if (h_total) (void)hipHostFree(h_total);
+        if (h_stats) (void)hipHostFree(h_stats);
+        if (stage) (void)hipFree(stage);
+        for (void *p : extra) (void)hipFree(p);
+    }
+};
+
+struct WorkspacePool {
+    std::mutex mu;
+    std::vector<std::unique_ptr<Workspace>> ws;
+
+    // The workspace of `s`, created on first use for a grid of n_blocks.
+    int get(hipStream_t s, int n_blocks, Workspace **out) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &p : ws)
+            if (p->stream == s && p->n_blocks == n_blocks) {
+                *out = p.get();
+                return PFSM_OK;
+            }
+        auto w = std::make_unique<Workspace>();
+        w->stream = s;
+        w->n_blocks = n_blocks;
+        HIP_TRY(hipMalloc(&w->slots, sizeof(unsigned long long) * n_blocks));
+        HIP_TRY(hipMemset(w->slots, 0, sizeof(unsigned long long) * n_blocks));
+        HIP_TRY(hipMalloc(&w->bstats, sizeof(long long) * 4 * n_blocks));
+        HIP_TRY(hipMemset(w->bstats, 0, sizeof(long long) * 4 * n_blocks));
+        HIP_TRY(hipMalloc(&w->d_total, sizeof(int64_t)));
+        HIP_TRY(hipHostMalloc(&w->h_total, sizeof(int64_t), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(&w->h_stats, sizeof(long long) * 4 * n_blocks, hipHostMallocDefault));
+        HIP_TRY(hipDeviceSynchronize());
+        *out = w.get();
+        ws.push_back(std::move(w));
+        return PFSM_OK;
+    }
+
+    Workspace *find(hipStream_t s) {
+        std::lock_guard<std::mutex> lk(mu);
+        Workspace *r = nullptr;
+        for (auto &p : ws)
+            if (p->stream == s && p->scanned) r = p.get();
+        return r;
+    }
+};
+
+// The scan kernels read 16-byte granules and need a 16-byte aligned input:
+// a misaligned input is first copied (in stream order) into a buffer of the
+// workspace.  *x is replaced by the aligned pointer.
+inline int align_input(Workspace *w, const uint8_t **x, int64_t n, hipStream_t s) {
+    if ((reinterpret_cast<uintptr_t>(*x) & 15) == 0) return PFSM_OK;
+    if (w->stage_cap < n) {
+        HIP_TRY(hipStreamSynchronize(s));
+        if (w->stage) HIP_TRY(hipFree(w->stage));
+        w->stage = nullptr;
+        w->stage_cap = 0;
+        HIP_TRY(hipMalloc(&w->stage, (size_t)n));
+        w->stage_cap = n;
+    }
+    HIP_TRY(hipMemcpyAsync(w->stage, *x, (size_t)n, hipMemcpyDeviceToDevice, s));
+    *x = w->stage;
+    return PFSM_OK;
+}
+
+// Sum the per-workgroup counters of the last scan in `w` (synchronises).
+inline int workspace_stats(Workspace *w, long long v[4]) {
+    HIP_TRY(hipMemcpyAsync(w->h_stats, w->bstats, sizeof(long long) * 4 * w->n_blocks, hipMemcpyDeviceToHost,
+                           w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    for (int k = 0; k < 4; ++k) v[k] = 0;
+    for (int b = 0; b < w->n_blocks; ++b)
+        for (int k = 0; k < 4; ++k) v[k] += w->h_stats[4 * b + k];
+    return PFSM_OK;
+}
+
+// Compute units of the current device.
+int device_cus(int *out);
+
+// Split n bytes over a persistent grid of n_blocks workgroups: bytes per
+// workgroup and round (a multiple of 16) and the number of rounds.
+inline void plan_segments(int64_t n, int n_blocks, int64_t seg_target, int64_t *seg, int *rounds) {
+    int64_t per = (n + n_blocks - 1) / n_blocks;
+    per = (per + 15) / 16 * 16;
+    if (per < 16) per = 16;
+    if (per > seg_target) per = seg_target;
+    *seg = per;
+    *rounds = (int)((n + per * n_blocks - 1) / (per * n_blocks));
+    if (*rounds < 1) *rounds = 1;
+}
+
+}  // namespace pfsmk

@@ -7,55 +7,77 @@
 
 namespace pfsmk {
 
-constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
-constexpr int kOverlap = 256;      // bytes staged past a window's end
-constexpr int kFlagsLds = 8192;    // state flags cached in LDS up to this many states
-
 // Per-state flag bits (a byte per state).
 constexpr uint8_t kLive = 1;   // some final state with an enabled label is reachable
 constexpr uint8_t kFinal = 2;  // the state carries at least one enabled label
 
-// Decoupled look-back status word: 2 flag bits over a 62-bit count.
-constexpr unsigned long long kStatAgg = 1ull << 62;
-constexpr unsigned long long kStatPre = 2ull << 62;
-constexpr unsigned long long kStatVal = (1ull << 62) - 1;
-
-// Control block of one scan workspace.  ticket/done return to zero at the
-// end of every launch (the last workgroup to finish resets them and the
-// status words), so consecutive launches on one stream need no memset.
-struct ScanCtl {
-    unsigned int ticket;
-    unsigned int done;
-    unsigned long long acc[4];  // running T, X, long walks, matches
-    long long last[4];          // the previous launch's totals
-};
+// Cross-workgroup count slot: a 24-bit epoch over a 40-bit count.  Every
+// workgroup of the persistent grid rewrites its slot once per round, so all
+// slots always carry the same epoch when a launch begins; a workgroup reads
+// its own slot's epoch, adds one, and waits for its peers to reach it.
+constexpr int kEpochShift = 40;
+constexpr unsigned long long kCountMask = (1ull << kEpochShift) - 1;
+constexpr unsigned kEpochMask = (1u << 24) - 1;
 
 struct MatchOut {
     int32_t start, end, label;
 };
 
-// DFA scan arguments.
-struct DfaArgs {
-    const uint8_t *x;
-    int64_t n;
-    const void *tbl;          // int16 or int32 [n_states * n_symbols], as given
-    int32_t n_states, n_symbols;
-    const int16_t *b2s;       // [256] byte -> symbol, -1 = not in the alphabet
-    const int32_t *first;     // [256] live target of q0 on each byte, else -1
-    const uint8_t *flags;     // [n_states] kLive | kFinal
-    const int32_t *lab_off;   // [n_states + 1]
-    const int32_t *lab;       // enabled labels, sorted and unique per state
-    MatchOut *out;
-    int64_t cap;
-    int64_t *total;           // grand total (device)
-    ScanCtl *ctl;
-    unsigned long long *status;  // [n_windows]
-    int32_t n_windows;
+// ---------------------------------------------------------------- DFA scan
+
+constexpr int kDfaThreads = 1024;              // one workgroup, 16 wave64
+constexpr int kDfaWindow = kDfaThreads * 16;   // 16 bytes per thread
+constexpr int kDfaSegMax = 65536;              // bytes per workgroup and round
+constexpr int kDfaQueue = 128;                 // LDS queue entries per wave
+constexpr int kDfaMatchCap = 1024;             // LDS match buffer per workgroup
+constexpr int kDfaLdsLimit = 160 * 1024;       // LDS per compute unit (gfx950)
+constexpr int kDfaTableBudget = 96 * 1024;     // resident table bytes
+constexpr int kDfaHotBudget = 48 * 1024;       // cached rows when not resident
+
+// How the transition table is read.  Resident encodings keep the whole
+// table, the state flags and the label CSR in LDS; the cold ones read them
+// through L2 (rows of q0's successors are still copied to LDS).  Every
+// encoding decodes to the given values.
+enum DfaEnc : int {
+    kEnc8 = 0,    // n_states <= 255: uint8, 255 stands for -1
+    kEnc8D = 1,   // n_states == 256: uint8 low byte + one "no transition" bit
+    kEnc16 = 2,   // n_states <= 32767: int16
+    kCold16 = 3,  // int16 in HBM/L2
+    kCold32 = 4,  // int32 in HBM/L2
 };
 
-// Host-side launchers (defined in the .hip translation units).
-hipError_t launch_dfa_scan(const DfaArgs &a, int per_thread, bool identity_map, bool tbl16,
-                           hipStream_t stream);
+struct DfaArgs {
+    const uint8_t *x;           // 16-byte aligned
+    int64_t n;
+    const void *tbl;            // table as stored in HBM (int16 or int32)
+    const void *res;            // resident encoding image (LDS copy source)
+    int32_t res_bytes;
+    int32_t n_states, n_symbols;
+    const int16_t *b2s;         // [256] byte -> symbol, -1 = not in the alphabet
+    const int32_t *first;       // [256] live target of q0 on each byte, else -1
+    const int16_t *first_slot;  // [256] row slot of first[b] in the cached rows, -1 = none
+    const void *hot;            // cold encodings: [n_hot * n_symbols] cached rows
+    int32_t n_hot;
+    const uint8_t *flags;       // [n_states] kLive | kFinal
+    const int32_t *lab_off;     // [n_states + 1]
+    const int32_t *lab;         // enabled labels, sorted and unique per state
+    MatchOut *out;
+    int64_t cap;
+    int64_t *total;             // grand total (device)
+    unsigned long long *slots;  // [n_blocks] epoch | count
+    long long *bstats;          // [n_blocks * 4] T, X, long walks, matches
+    int64_t seg;                // bytes per workgroup per round (multiple of 16)
+    int32_t n_blocks;           // persistent grid size
+    int32_t n_rounds;
+    // dynamic LDS layout, byte offsets
+    int32_t off_flags, off_laboff, off_lab, off_tab, off_q, off_m, lds_bytes;
+};
+
+// Fixed part of the DFA kernel's dynamic LDS (window, q0 row, slots, map).
+constexpr int kDfaLdsFixed = kDfaWindow + 256 * 4 + 256 * 2 + 256 * 2;
+
+// Host-side kernel handles (defined in the .hip translation units).
+const void *dfa_kernel_fn(int enc, bool identity_map);
 hipError_t launch_write_zero(int64_t *p, hipStream_t stream);
 
 }  // namespace pfsmk

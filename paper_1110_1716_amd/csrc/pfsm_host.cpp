@@ -1,167 +1,63 @@
-// Host side of libpfsm: descriptor validation, the read-only caches derived
-// from an automaton, device upload, per-stream scan workspaces and the C ABI
-// declared in include/pfsm.h.
+// Host side of libpfsm: the C ABI declared in include/pfsm.h, DFA descriptor
+// validation, the read-only caches derived from a DFA, device upload and the
+// launch of the DFA scan.  The NFA half lives in nfa_host.cpp.
 #include "pfsm.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdarg>
-#include <cstdio>
 #include <cstring>
 #include <memory>
-#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
+#include "host_common.h"
 #include "pfsm_dev.h"
 #include "pfsm_nfa.h"
 
 using namespace pfsmk;
 
-namespace {
+namespace pfsmk {
 
-thread_local std::string g_err;
-
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
+std::string &last_error() {
+    thread_local std::string s;
+    return s;
 }
 
-#define HIP_TRY(expr)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(PFSM_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
-                        __FILE__, __LINE__);                                            \
-    } while (0)
+int device_cus(int *out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(out, hipDeviceAttributeMultiprocessorCount, dev));
+    return PFSM_OK;
+}
 
-// A device buffer owned by a handle.
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    int alloc(size_t n) {
-        release();
-        if (n == 0) n = 1;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return fail(e == hipErrorOutOfMemory ? PFSM_ENOMEM : PFSM_EHIP, "hipMalloc(%zu): %s", n,
-                        hipGetErrorString(e));
-        }
-        bytes = n;
-        return PFSM_OK;
-    }
-    template <typename T>
-    int upload(const T *src, size_t count, hipStream_t s) {
-        int rc = alloc(count * sizeof(T));
-        if (rc) return rc;
-        if (count) HIP_TRY(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
-        return PFSM_OK;
-    }
-    template <typename T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
-// Scan scratch for one stream: look-back status words, the control block,
-// the device total and a pinned host slot for reading it back.
-struct Workspace {
-    hipStream_t stream = nullptr;
-    ScanCtl *ctl = nullptr;
-    unsigned long long *status = nullptr;
-    int64_t status_cap = 0;
-    int64_t *d_total = nullptr;
-    int64_t *h_total = nullptr;
-    long long *h_last = nullptr;
-    bool scanned = false;
-    std::vector<void *> extra;  // kernel-specific scratch, freed with the workspace
-
-    ~Workspace() {
-        if (ctl) (void)hipFree(ctl);
-        if (status) (void)hipFree(status);
-        if (d_total) (void)hipFree(d_total);
-        if (h_total) (void)hipHostFree(h_total);
-        if (h_last) (void)hipHostFree(h_last);
-        for (void *p : extra) (void)hipFree(p);
-    }
-};
-
-}  // namespace
+}  // namespace pfsmk
 
 struct pfsm {
     int kind = 0;  // 0 = DFA, 1 = NFA
     // ---- DFA: host copy (used to rebuild caches when a label is removed)
     int32_t n_states = 0, n_symbols = 0, q0 = 0;
     bool identity = true;
-    std::vector<int16_t> b2s;       // [256]
-    std::vector<int32_t> delta;     // [n_states * n_symbols]
+    std::vector<int16_t> b2s;                  // [256]
+    std::vector<int32_t> delta;                // [n_states * n_symbols]
     std::vector<std::vector<int32_t>> labels;  // per state: sorted unique labels
-    std::vector<int32_t> disabled;  // removed labels (sorted)
-    // ---- DFA: device
-    DevBuf d_tbl, d_b2s, d_first, d_flags, d_lab_off, d_lab;
+    std::vector<int32_t> disabled;             // removed labels (sorted)
+    // ---- DFA: device tables and the kernel's launch shape
+    DevBuf d_tbl, d_res, d_b2s, d_first, d_first_slot, d_flags, d_lab_off, d_lab;
     bool tbl16 = true;
+    int enc = kCold16;
+    int32_t res_bytes = 0, n_hot = 0;
+    int32_t off_flags = 0, off_laboff = 0, off_lab = 0, off_tab = 0, off_q = 0, off_m = 0, lds_bytes = 0;
+    int n_blocks = 0;
+    const void *kernel = nullptr;
     // ---- NFA
     NfaPtr nfa;
-    // ---- workspaces
-    std::mutex ws_mu;
-    std::vector<std::unique_ptr<Workspace>> ws;
+    // ---- scan workspaces, one per stream
+    WorkspacePool pool;
 };
 
 namespace {
-
-// ------------------------------------------------------------------ workspaces
-
-int get_workspace(pfsm_t *h, hipStream_t s, int64_t n_windows, Workspace **out) {
-    std::lock_guard<std::mutex> lk(h->ws_mu);
-    Workspace *w = nullptr;
-    for (auto &p : h->ws)
-        if (p->stream == s) w = p.get();
-    if (!w) {
-        auto nw = std::make_unique<Workspace>();
-        nw->stream = s;
-        HIP_TRY(hipMalloc(&nw->ctl, sizeof(ScanCtl)));
-        HIP_TRY(hipMemset(nw->ctl, 0, sizeof(ScanCtl)));
-        HIP_TRY(hipMalloc(&nw->d_total, sizeof(int64_t)));
-        HIP_TRY(hipHostMalloc(&nw->h_total, sizeof(int64_t), hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc(&nw->h_last, 4 * sizeof(long long), hipHostMallocDefault));
-        HIP_TRY(hipDeviceSynchronize());
-        w = nw.get();
-        h->ws.push_back(std::move(nw));
-    }
-    if (n_windows > w->status_cap) {
-        // Earlier launches on this stream may still read the old array.
-        HIP_TRY(hipStreamSynchronize(s));
-        if (w->status) HIP_TRY(hipFree(w->status));
-        w->status = nullptr;
-        int64_t cap = std::max<int64_t>(n_windows, 1024);
-        hipError_t e = hipMalloc(&w->status, cap * sizeof(unsigned long long));
-        if (e != hipSuccess)
-            return fail(e == hipErrorOutOfMemory ? PFSM_ENOMEM : PFSM_EHIP, "status alloc: %s",
-                        hipGetErrorString(e));
-        HIP_TRY(hipMemset(w->status, 0, cap * sizeof(unsigned long long)));
-        HIP_TRY(hipDeviceSynchronize());
-        w->status_cap = cap;
-    }
-    *out = w;
-    return PFSM_OK;
-}
-
-// ------------------------------------------------------------------ validation helpers
 
 int check_labels(int32_t n_states, const int32_t *off, const int32_t *lab) {
     if (!off) return fail(PFSM_EINVAL, "final_off is NULL");
@@ -190,11 +86,12 @@ bool has_label(const std::vector<int32_t> &sorted, int32_t l) {
     return std::binary_search(sorted.begin(), sorted.end(), l);
 }
 
-// ------------------------------------------------------------------ DFA caches
+int align16(int v) { return (v + 15) & ~15; }
 
-// Rebuild and upload the caches that depend on the enabled label sets:
+// Rebuild and upload every cache that depends on the enabled label sets:
 // live flags (reverse search from states with an enabled label over
-// transitions that some byte can take), the q0 row per byte, label CSR.
+// transitions some byte can take), the q0 row per byte, the LDS copies of the
+// rows of q0's successors, label CSR; then the LDS layout and grid size.
 int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     const int32_t N = h->n_states, S = h->n_symbols;
     std::vector<std::vector<int32_t>> en(N);
@@ -205,7 +102,6 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     std::vector<uint8_t> sym_used(S, 0);
     for (int b = 0; b < 256; ++b)
         if (h->b2s[b] >= 0) sym_used[h->b2s[b]] = 1;
-    // reverse adjacency
     std::vector<int32_t> roff(N + 1, 0);
     for (int64_t i = 0; i < (int64_t)N * S; ++i)
         if (h->delta[i] >= 0 && sym_used[i % S]) roff[h->delta[i] + 1]++;
@@ -229,9 +125,9 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
             }
     std::vector<int32_t> first(256, -1);
     for (int b = 0; b < 256; ++b) {
-        int sym = h->b2s[b];
+        const int sym = h->b2s[b];
         if (sym < 0) continue;
-        int32_t t = h->delta[(int64_t)h->q0 * S + sym];
+        const int32_t t = h->delta[(int64_t)h->q0 * S + sym];
         if (t >= 0 && (flags[t] & kLive)) first[b] = t;
     }
     std::vector<int32_t> off(N + 1, 0), lab;
@@ -239,12 +135,107 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
         lab.insert(lab.end(), en[q].begin(), en[q].end());
         off[q + 1] = (int32_t)lab.size();
     }
+
+    // Transition table image for LDS.  A resident encoding keeps the whole
+    // table, the flags and the label CSR in LDS; when none fits, the table is
+    // read through L2 and the rows of q0's live successors are copied.
+    const int64_t ns = (int64_t)N * S;
+    std::vector<uint8_t> res;
+    std::vector<int16_t> first_slot(256, -1);
+    int n_hot = 0;
+    int enc = -1;
+    auto lds_total = [&](int64_t tab_bytes, bool resident) {
+        int64_t off = align16(kDfaLdsFixed);
+        if (resident) {
+            off = align16(off + N);
+            off = align16(off + (N + 1) * 4);
+            off = align16(off + (int64_t)lab.size() * 4);
+        }
+        off = align16(off + (tab_bytes + 15) / 16 * 16 + 16);
+        off += (kDfaThreads / 64) * kDfaQueue * 16;
+        return off + kDfaMatchCap * 12;
+    };
+    const int64_t bytes8 = ns, bytes8d = ((ns + 3) & ~3ll) + (ns + 31) / 32 * 4, bytes16 = ns * 2;
+    if (N <= 255 && bytes8 <= kDfaTableBudget && lds_total(bytes8, true) <= kDfaLdsLimit) {
+        enc = kEnc8;
+        res.resize(ns);
+        for (int64_t i = 0; i < ns; ++i) res[i] = h->delta[i] < 0 ? 255 : (uint8_t)h->delta[i];
+    } else if (N == 256 && bytes8d <= kDfaTableBudget && lds_total(bytes8d, true) <= kDfaLdsLimit) {
+        enc = kEnc8D;
+        const int64_t dead_off = (ns + 3) & ~3ll;
+        res.assign(bytes8d, 0);
+        uint32_t *dead = reinterpret_cast<uint32_t *>(res.data() + dead_off);
+        for (int64_t i = 0; i < ns; ++i) {
+            if (h->delta[i] < 0) dead[i >> 5] |= 1u << (i & 31);
+            else res[i] = (uint8_t)h->delta[i];
+        }
+    } else if (N <= 32767 && bytes16 <= kDfaTableBudget && lds_total(bytes16, true) <= kDfaLdsLimit) {
+        enc = kEnc16;
+        res.resize(bytes16);
+        int16_t *t = reinterpret_cast<int16_t *>(res.data());
+        for (int64_t i = 0; i < ns; ++i) t[i] = (int16_t)h->delta[i];
+    } else {
+        enc = h->tbl16 ? kCold16 : kCold32;
+        const int elem = h->tbl16 ? 2 : 4;
+        const int max_hot = (int)std::min<int64_t>(32767, kDfaHotBudget / ((int64_t)S * elem));
+        std::vector<std::pair<int, int32_t>> freq;  // (-bytes leading there, state)
+        std::vector<int32_t> tg;
+        for (int b = 0; b < 256; ++b)
+            if (first[b] >= 0) tg.push_back(first[b]);
+        std::sort(tg.begin(), tg.end());
+        for (size_t i = 0; i < tg.size();) {
+            size_t j = i;
+            while (j < tg.size() && tg[j] == tg[i]) ++j;
+            freq.push_back({-(int)(j - i), tg[i]});
+            i = j;
+        }
+        std::sort(freq.begin(), freq.end());
+        std::vector<int32_t> hot_states;
+        for (auto &f : freq)
+            if ((int)hot_states.size() < max_hot) hot_states.push_back(f.second);
+        for (int b = 0; b < 256; ++b)
+            for (size_t k = 0; k < hot_states.size(); ++k)
+                if (first[b] == hot_states[k]) first_slot[b] = (int16_t)k;
+        n_hot = (int)hot_states.size();
+        res.resize((size_t)n_hot * S * elem);
+        for (int k = 0; k < n_hot; ++k)
+            for (int sy = 0; sy < S; ++sy) {
+                const int32_t v = h->delta[(int64_t)hot_states[k] * S + sy];
+                if (elem == 2) reinterpret_cast<int16_t *>(res.data())[(int64_t)k * S + sy] = (int16_t)v;
+                else reinterpret_cast<int32_t *>(res.data())[(int64_t)k * S + sy] = v;
+            }
+    }
+    res.resize((res.size() + 15) / 16 * 16 + 16, 0);  // whole 16-byte copies
+    const bool resident = enc == kEnc8 || enc == kEnc8D || enc == kEnc16;
+    h->off_flags = align16(kDfaLdsFixed);
+    h->off_laboff = align16(h->off_flags + (resident ? N : 0));
+    h->off_lab = align16(h->off_laboff + (resident ? (N + 1) * 4 : 0));
+    h->off_tab = align16(h->off_lab + (resident ? (int)lab.size() * 4 : 0));
+    h->off_q = align16(h->off_tab + (int)res.size());
+    h->off_m = h->off_q + (kDfaThreads / 64) * kDfaQueue * 16;
+    h->lds_bytes = h->off_m + kDfaMatchCap * 12;
+    if (h->lds_bytes > kDfaLdsLimit) return fail(PFSM_EINVAL, "DFA scan LDS layout does not fit");
+
     int rc;
     if ((rc = h->d_first.upload(first.data(), 256, s))) return rc;
+    if ((rc = h->d_first_slot.upload(first_slot.data(), 256, s))) return rc;
+    if ((rc = h->d_res.upload(res.data(), res.size(), s))) return rc;
     if ((rc = h->d_flags.upload(flags.data(), N, s))) return rc;
     if ((rc = h->d_lab_off.upload(off.data(), N + 1, s))) return rc;
     if ((rc = h->d_lab.upload(lab.data(), lab.size(), s))) return rc;
     HIP_TRY(hipStreamSynchronize(s));
+    h->enc = enc;
+    h->n_hot = n_hot;
+    h->res_bytes = (int32_t)res.size();
+
+    h->kernel = dfa_kernel_fn(enc, h->identity);
+    if (!h->kernel) return fail(PFSM_EINVAL, "no DFA kernel for encoding %d", enc);
+    HIP_TRY(hipFuncSetAttribute(h->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, h->lds_bytes));
+    int occ = 0, cus = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, h->kernel, kDfaThreads, h->lds_bytes));
+    if ((rc = device_cus(&cus))) return rc;
+    if (occ < 1) return fail(PFSM_EINVAL, "DFA scan kernel does not fit on a compute unit");
+    h->n_blocks = occ * cus;
     return PFSM_OK;
 }
 
@@ -268,7 +259,7 @@ const char *pfsm_strerror(int code) {
     }
 }
 
-const char *pfsm_last_error(void) { return g_err.c_str(); }
+const char *pfsm_last_error(void) { return last_error().c_str(); }
 
 int pfsm_load_dfa(pfsm_t **out, const pfsm_dfa_desc *d, void *hip_stream) {
     if (!out || !d) return fail(PFSM_EINVAL, "NULL argument");
@@ -322,9 +313,8 @@ int pfsm_load_nfa(pfsm_t **out, const pfsm_nfa_desc *d, void *hip_stream) {
     std::unique_ptr<pfsm_t> h(new (std::nothrow) pfsm_t);
     if (!h) return fail(PFSM_ENOMEM, "handle");
     h->kind = 1;
-    std::string err;
-    int rc = nfa_load(d, static_cast<hipStream_t>(hip_stream), &h->nfa, &err);
-    if (rc) return fail(rc, "%s", err.c_str());
+    int rc = nfa_load(d, static_cast<hipStream_t>(hip_stream), &h->nfa);
+    if (rc) return rc;
     *out = h.release();
     return PFSM_OK;
 }
@@ -333,38 +323,26 @@ int pfsm_add_pattern(pfsm_t *h, const pfsm_nfa_desc *pattern, void *hip_stream) 
     if (!h || !pattern) return fail(PFSM_EINVAL, "NULL argument");
     if (h->kind == 0)
         return fail(PFSM_ENOSYS, "a DFA handle is one monolithic table; load the union as an NFA");
-    std::string err;
-    int rc = nfa_add_pattern(h->nfa.get(), pattern, static_cast<hipStream_t>(hip_stream), &err);
-    if (rc) return fail(rc, "%s", err.c_str());
-    return PFSM_OK;
+    return nfa_add_pattern(h->nfa.get(), pattern, static_cast<hipStream_t>(hip_stream));
 }
 
 int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream) {
     if (!h) return fail(PFSM_EINVAL, "NULL handle");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (h->kind == 1) {
-        std::string err;
-        int rc = nfa_remove_pattern(h->nfa.get(), label, s, &err);
-        if (rc) return fail(rc, "%s", err.c_str());
-        return PFSM_OK;
-    }
+    if (h->kind == 1) return nfa_remove_pattern(h->nfa.get(), label, s);
     if (has_label(h->disabled, label)) return fail(PFSM_ENOENT, "label %d already removed", label);
     bool found = false;
     for (auto &v : h->labels)
-        if (has_label(v, label)) { found = true; break; }
+        if (has_label(v, label)) {
+            found = true;
+            break;
+        }
     if (!found) return fail(PFSM_ENOENT, "no final state carries label %d", label);
     h->disabled.insert(std::upper_bound(h->disabled.begin(), h->disabled.end(), label), label);
-    // Scans already on the stream read the current caches; wait for them,
-    // then replace the caches in place.
-    HIP_TRY(hipStreamSynchronize(s));
+    // Scans already issued read the current caches: wait for the device,
+    // then replace the caches.
+    HIP_TRY(hipDeviceSynchronize());
     return dfa_upload_caches(h, s);
-}
-
-static int choose_per_thread(int64_t n) {
-    // Windows of 256 * B bytes; keep enough windows to fill 256 CUs.
-    if (n >= (int64_t)4096 * 256 * 4) return 16;
-    if (n >= (int64_t)1024 * 256 * 4) return 4;
-    return 1;
 }
 
 int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
@@ -380,37 +358,44 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
         HIP_TRY(launch_write_zero(d_n_matches, s));
         return PFSM_OK;
     }
-    if (h->kind == 1) {
-        std::string err;
-        int rc = nfa_scan_async(h->nfa.get(), d_input, n, reinterpret_cast<MatchOut *>(d_out), cap,
-                                d_n_matches, s, &err);
-        if (rc) return fail(rc, "%s", err.c_str());
-        return PFSM_OK;
-    }
-    const int B = choose_per_thread(n);
-    const int64_t W = (int64_t)kBlock * B;
-    const int64_t G = (n + W - 1) / W;
+    if (h->kind == 1)
+        return nfa_scan_async(h->nfa.get(), d_input, n, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, s);
     Workspace *w;
-    int rc = get_workspace(h, s, G, &w);
+    int rc = h->pool.get(s, h->n_blocks, &w);
     if (rc) return rc;
+    if ((rc = align_input(w, &d_input, n, s))) return rc;
     DfaArgs a;
+    std::memset(&a, 0, sizeof a);
     a.x = d_input;
     a.n = n;
     a.tbl = h->d_tbl.p;
+    a.res = h->d_res.p;
+    a.res_bytes = h->res_bytes;
     a.n_states = h->n_states;
     a.n_symbols = h->n_symbols;
     a.b2s = h->d_b2s.as<int16_t>();
     a.first = h->d_first.as<int32_t>();
+    a.first_slot = h->d_first_slot.as<int16_t>();
+    a.n_hot = h->n_hot;
     a.flags = h->d_flags.as<uint8_t>();
     a.lab_off = h->d_lab_off.as<int32_t>();
     a.lab = h->d_lab.as<int32_t>();
     a.out = reinterpret_cast<MatchOut *>(d_out);
     a.cap = cap;
     a.total = d_n_matches;
-    a.ctl = w->ctl;
-    a.status = w->status;
-    a.n_windows = (int32_t)G;
-    HIP_TRY(launch_dfa_scan(a, B, h->identity, h->tbl16, s));
+    a.slots = w->slots;
+    a.bstats = w->bstats;
+    a.n_blocks = h->n_blocks;
+    plan_segments(n, h->n_blocks, kDfaSegMax, &a.seg, &a.n_rounds);
+    a.off_flags = h->off_flags;
+    a.off_laboff = h->off_laboff;
+    a.off_lab = h->off_lab;
+    a.off_tab = h->off_tab;
+    a.off_q = h->off_q;
+    a.off_m = h->off_m;
+    a.lds_bytes = h->lds_bytes;
+    void *args[] = {&a};
+    HIP_TRY(hipLaunchCooperativeKernel(h->kernel, dim3(h->n_blocks), dim3(kDfaThreads), args, h->lds_bytes, s));
     w->scanned = true;
     return PFSM_OK;
 }
@@ -420,7 +405,8 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
     if (!h || !n_matches) return fail(PFSM_EINVAL, "NULL argument");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Workspace *w;
-    int rc = get_workspace(h, s, 0, &w);
+    const int nb = h->kind == 1 ? nfa_grid_blocks(h->nfa.get()) : h->n_blocks;
+    int rc = (h->kind == 1 ? nfa_pool(h->nfa.get()) : &h->pool)->get(s, nb, &w);
     if (rc) return rc;
     rc = pfsm_scan_async(h, d_input, n, d_out, cap, w->d_total, hip_stream);
     if (rc) return rc;
@@ -432,10 +418,9 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
     return PFSM_OK;
 }
 
-int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data,
-                    const int64_t *d_stream_off, const int32_t *d_stream_automaton, int32_t n_streams,
-                    pfsm_match_t *d_out, int64_t cap, int64_t *d_match_off, int64_t *n_matches,
-                    void *hip_stream) {
+int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
+                    const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
+                    int64_t *d_match_off, int64_t *n_matches, void *hip_stream) {
     (void)hs; (void)n_automata; (void)d_data; (void)d_stream_off; (void)d_stream_automaton;
     (void)n_streams; (void)d_out; (void)cap; (void)d_match_off; (void)n_matches; (void)hip_stream;
     return fail(PFSM_ENOSYS, "pfsm_scan_batch is not available yet");
@@ -444,27 +429,15 @@ int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data
 int pfsm_last_stats(pfsm_t *h, pfsm_stats *out, void *hip_stream) {
     if (!h || !out) return fail(PFSM_EINVAL, "NULL argument");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    Workspace *w = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(h->ws_mu);
-        for (auto &p : h->ws)
-            if (p->stream == s) w = p.get();
-    }
-    if (h->kind == 1) {
-        std::string err;
-        long long v[4];
-        int rc = nfa_last_stats(h->nfa.get(), s, v, &err);
-        if (rc) return fail(rc, "%s", err.c_str());
-        out->transitions = v[0]; out->activations = v[1]; out->long_walks = v[2]; out->matches = v[3];
-        return PFSM_OK;
-    }
-    if (!w || !w->scanned) return fail(PFSM_ENOENT, "no scan on this stream yet");
-    HIP_TRY(hipMemcpyAsync(w->h_last, w->ctl->last, 4 * sizeof(long long), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    out->transitions = w->h_last[0];
-    out->activations = w->h_last[1];
-    out->long_walks = w->h_last[2];
-    out->matches = w->h_last[3];
+    Workspace *w = (h->kind == 1 ? nfa_pool(h->nfa.get()) : &h->pool)->find(s);
+    if (!w) return fail(PFSM_ENOENT, "no scan on this stream yet");
+    long long v[4];
+    int rc = workspace_stats(w, v);
+    if (rc) return rc;
+    out->transitions = v[0];
+    out->activations = v[1];
+    out->long_walks = v[2];
+    out->matches = v[3];
     return PFSM_OK;
 }
 

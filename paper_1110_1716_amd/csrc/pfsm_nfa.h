@@ -1,11 +1,11 @@
-// NFA side of the host library (internal).
+// NFA half of the host library (internal).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <memory>
-#include <string>
 
+#include "host_common.h"
 #include "pfsm.h"
 #include "pfsm_dev.h"
 
@@ -17,11 +17,12 @@ struct NfaDeleter {
 };
 using NfaPtr = std::unique_ptr<NfaHost, NfaDeleter>;
 
-int nfa_load(const pfsm_nfa_desc *d, hipStream_t s, NfaPtr *out, std::string *err);
-int nfa_add_pattern(NfaHost *h, const pfsm_nfa_desc *p, hipStream_t s, std::string *err);
-int nfa_remove_pattern(NfaHost *h, int32_t label, hipStream_t s, std::string *err);
+int nfa_load(const pfsm_nfa_desc *d, hipStream_t s, NfaPtr *out);
+int nfa_add_pattern(NfaHost *h, const pfsm_nfa_desc *p, hipStream_t s);
+int nfa_remove_pattern(NfaHost *h, int32_t label, hipStream_t s);
 int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap, int64_t *d_total,
-                   hipStream_t s, std::string *err);
-int nfa_last_stats(NfaHost *h, hipStream_t s, long long v[4], std::string *err);
+                   hipStream_t s);
+int nfa_grid_blocks(NfaHost *h);
+WorkspacePool *nfa_pool(NfaHost *h);
 
 }  // namespace pfsmk

@@ -1,6 +1,6 @@
 // Device helpers shared by the scan kernels: wave64 compaction, block
-// reductions and the decoupled look-back that turns per-window match counts
-// into global output offsets in a single pass.
+// reductions, 16-byte input loads and the cross-workgroup prefix that turns
+// per-workgroup match counts into output offsets.
 #pragma once
 
 #include "pfsm_dev.h"
@@ -9,18 +9,17 @@ namespace pfsmk {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// Reserve one slot per lane with `pred` in an LDS queue: one LDS atomic per
-// wave, ranks from the ballot's prefix popcount.  Returns -1 when !pred.
-__device__ __forceinline__ int wave_reserve(int *counter, bool pred) {
+__device__ __forceinline__ unsigned long long lanes_below() {
+    return (1ull << lane_id()) - 1ull;
+}
+
+// Reserve one slot per lane with `pred` in a wave-private LDS queue whose
+// count lives in a wave-uniform register.  Returns the slot or -1.
+__device__ __forceinline__ int wave_push_slot(int &count, bool pred) {
     const unsigned long long m = __ballot(pred);
-    if (m == 0) return -1;
-    const int lane = lane_id();
-    const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, leader);
-    const int rank = __popcll(m & ((1ull << lane) - 1ull));
-    return pred ? base + rank : -1;
+    const int slot = count + __popcll(m & lanes_below());
+    count += __popcll(m);
+    return pred ? slot : -1;
 }
 
 __device__ __forceinline__ long long wave_sum(long long v) {
@@ -40,8 +39,9 @@ __device__ __forceinline__ long long wave_incl_scan(long long v) {
     return v;
 }
 
-// Sum of `v` over the block; every thread gets the result.  `red` holds
-// kBlock/64 slots.  Contains two barriers.
+// Sum of `v` over a block of NT threads; every thread gets the result.
+// `red` holds NT/64 slots.  Contains two barriers.
+template <int NT>
 __device__ __forceinline__ long long block_sum(long long v, long long *red) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
@@ -49,13 +49,35 @@ __device__ __forceinline__ long long block_sum(long long v, long long *red) {
     __syncthreads();
     long long s = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
     __syncthreads();
     return s;
 }
 
-// Exclusive scan of `v` over the block in thread order; *total receives the
-// sum.  `red` holds kBlock/64 slots.  Contains two barriers.
+// Sums of four values over a block of NT threads (every thread gets them).
+// `red` holds 4 * NT/64 slots.  Contains two barriers.
+template <int NT>
+__device__ __forceinline__ void block_sum4(long long v[4], long long *red) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long long s = wave_sum(v[k]);
+        if (lane_id() == 0) red[4 * w + k] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        long long s = 0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) s += red[4 * i + k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// Exclusive scan of `v` over a block of NT threads in thread order; *total
+// receives the sum.  `red` holds NT/64 slots.  Contains two barriers.
+template <int NT>
 __device__ __forceinline__ long long block_excl_scan(long long v, long long *red, long long *total) {
     const long long inc = wave_incl_scan(v);
     const int w = threadIdx.x >> 6;
@@ -63,7 +85,7 @@ __device__ __forceinline__ long long block_excl_scan(long long v, long long *red
     __syncthreads();
     long long before = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) {
+    for (int i = 0; i < NT / 64; ++i) {
         if (i < w) before += red[i];
         all += red[i];
     }
@@ -72,90 +94,62 @@ __device__ __forceinline__ long long block_excl_scan(long long v, long long *red
     return before + inc - v;
 }
 
-__device__ __forceinline__ unsigned long long status_load(const unsigned long long *p) {
+__device__ __forceinline__ unsigned long long slot_load(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void status_store(unsigned long long *p, unsigned long long v) {
+__device__ __forceinline__ void slot_store(unsigned long long *p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Decoupled look-back, run by one whole wave for window `w` whose own count
-// is `mine`.  Publishes the aggregate, walks predecessors 64 at a time until
-// an inclusive prefix is found, publishes its own inclusive prefix and
-// returns the exclusive prefix (in every lane).  Windows are numbered in
-// ticket order, so every predecessor is already running and publishes its
-// aggregate without waiting on anyone: the spin always ends.
-__device__ __forceinline__ long long lookback(unsigned long long *status, long long w, long long mine) {
-    const int lane = lane_id();
-    if (w == 0) {
-        if (lane == 0) status_store(&status[0], kStatPre | (unsigned long long)mine);
-        return 0;
-    }
-    if (lane == 0) status_store(&status[w], kStatAgg | (unsigned long long)mine);
-    long long excl = 0;
-    long long look = w - 1;
-    for (;;) {
-        const long long idx = look - lane;
-        unsigned long long v = idx >= 0 ? status_load(&status[idx]) : kStatPre;
-        while (__any((v >> 62) == 0)) {
-            __builtin_amdgcn_s_sleep(1);
-            if ((v >> 62) == 0) v = status_load(&status[idx]);
-        }
-        const unsigned long long pm = __ballot((v >> 62) == 2);
-        const long long val = (long long)(v & kStatVal);
-        if (pm) {
-            const int j = __ffsll((long long)pm) - 1;
-            excl += wave_sum(lane <= j ? val : 0);
-            break;
-        }
-        excl += wave_sum(val);
-        look -= 64;
-    }
-    if (lane == 0) status_store(&status[w], kStatPre | (unsigned long long)(excl + mine));
-    return excl;
+// The epoch this launch starts with: one past the epoch of the workgroup's
+// own slot (every slot carries the same epoch between launches).
+__device__ __forceinline__ unsigned first_epoch(const unsigned long long *slots, int b) {
+    return (unsigned)((slot_load(&slots[b]) >> kEpochShift) + 1) & kEpochMask;
 }
 
-// End-of-launch bookkeeping: add this block's counters, and let the last
-// block to finish publish the launch's totals and reset the control block and
-// the status words for the next launch.  Call from every thread.
-__device__ __forceinline__ void finish_launch(ScanCtl *ctl, unsigned long long *status, int n_windows,
-                                              long long T, long long X, long long L, long long M,
-                                              int *last_flag) {
-    if (threadIdx.x == 0) {
-        if (T) atomicAdd(&ctl->acc[0], (unsigned long long)T);
-        if (X) atomicAdd(&ctl->acc[1], (unsigned long long)X);
-        if (L) atomicAdd(&ctl->acc[2], (unsigned long long)L);
-        if (M) atomicAdd(&ctl->acc[3], (unsigned long long)M);
-        __threadfence();
-        const unsigned prev = atomicAdd(&ctl->done, 1u);
-        *last_flag = (prev == (unsigned)(n_windows - 1));
-    }
-    __syncthreads();
-    if (*last_flag) {
-        __threadfence();
-        for (int i = threadIdx.x; i < n_windows; i += kBlock) status[i] = 0;
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) ctl->last[k] = (long long)atomicExch(&ctl->acc[k], 0ull);
-            ctl->ticket = 0;
-            ctl->done = 0;
+// Publish this workgroup's count for `epoch`, then read every peer's slot of
+// the same epoch.  Returns the sum over lower-numbered workgroups; *round
+// receives the sum over all of them.  Every workgroup of the grid is resident
+// (cooperative launch) and publishes before it waits, so the waits end.
+// Contains barriers; call from every thread.
+template <int NT>
+__device__ __forceinline__ long long grid_prefix(unsigned long long *slots, int nb, int b, unsigned epoch,
+                                                 long long mine, long long *red, long long *round) {
+    if (threadIdx.x == 0)
+        slot_store(&slots[b], ((unsigned long long)epoch << kEpochShift) | (unsigned long long)mine);
+    long long ex = 0, all = 0;
+    for (int j = threadIdx.x; j < nb; j += NT) {
+        long long c;
+        if (j == b) {
+            c = mine;
+        } else {
+            unsigned long long v = slot_load(&slots[j]);
+            while (((unsigned)(v >> kEpochShift) & kEpochMask) != epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                v = slot_load(&slots[j]);
+            }
+            c = (long long)(v & kCountMask);
         }
+        all += c;
+        if (j < b) ex += c;
     }
+    const long long e = block_sum<NT>(ex, red);
+    *round = block_sum<NT>(all, red);
+    return e;
 }
 
-// Stage x[0, len) into LDS (len <= capacity), 16 bytes per load when the
-// source is 16-byte aligned.
-__device__ __forceinline__ void stage_bytes(uint8_t *dst, const uint8_t *src, int len) {
-    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-        const int nv = len >> 4;
-        const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-        uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-        for (int c = threadIdx.x; c < nv; c += kBlock) d4[c] = s4[c];
-        for (int i = (nv << 4) + threadIdx.x; i < len; i += kBlock) dst[i] = src[i];
-    } else {
-        for (int i = threadIdx.x; i < len; i += kBlock) dst[i] = src[i];
-    }
+// The 16-byte granule of a 16-byte aligned input starting at `pos` (a
+// multiple of 16 below n).  Bytes at or past n are unspecified: callers never
+// use them.  The granule holds at least one valid byte, so it lies on a page
+// of the input and the load cannot fault.
+__device__ __forceinline__ uint4 load_granule(const uint8_t *x, int64_t pos) {
+    return *reinterpret_cast<const uint4 *>(x + pos);
+}
+
+__device__ __forceinline__ int byte_of(const uint4 &v, int k) {
+    const uint32_t w = k < 4 ? v.x : k < 8 ? v.y : k < 12 ? v.z : v.w;
+    return (int)((w >> (8 * (k & 3))) & 0xffu);
 }
 
 }  // namespace pfsmk
