@@ -85,7 +85,9 @@ struct Workspace {
     bool scanned = false;
     uint8_t *stage = nullptr;             // aligned copy of a misaligned input
     int64_t stage_cap = 0;
-    std::vector<void *> extra;            // kernel-specific scratch
+    uint32_t *big_front = nullptr;        // NFA replay frontiers
+    uint32_t *big_bits = nullptr;         // NFA replay visited bits (kept clear)
+    int64_t big_states = 0;
 
     ~Workspace() {
         if (slots) (void)hipFree(slots);
@@ -94,7 +96,8 @@ struct Workspace {
         if (h_total) (void)hipHostFree(h_total);
         if (h_stats) (void)hipHostFree(h_stats);
         if (stage) (void)hipFree(stage);
-        for (void *p : extra) (void)hipFree(p);
+        if (big_front) (void)hipFree(big_front);
+        if (big_bits) (void)hipFree(big_bits);
     }
 };
 

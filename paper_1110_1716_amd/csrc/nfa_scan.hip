@@ -1,0 +1,659 @@
+// All-matches NFA scan for gfx950 (Section III.B with epsilon transitions;
+// the NFA case of Section III.C).
+//
+// Persistent cooperative grid of 256-thread workgroups; workgroup b owns the
+// start positions of one contiguous segment per round (lazy data
+// partitioning, Section III.D.2).  For each start i the instance's state set
+// is advanced one symbol at a time (Section III.B steps 3-4), closed under
+// epsilon edges right after each symbol, and every label of every final
+// state in it is reported with end = the symbol's position.
+//   * Symbols one and two come from read-only caches derived from the
+//     automaton when it is loaded: the set after the first symbol for each
+//     byte (the epsilon closure of q0 needs no work per position) and, for
+//     each byte pair, the set after two symbols, located through a 64 Ki-bit
+//     bitmap in LDS.  Most instances end there.
+//   * Live instances keep their set in registers (up to kNfaK states, kept
+//     duplicate-free, so every state is expanded once per symbol) and wait in
+//     a wave-private LDS queue; each queue round advances every walk through
+//     the rest of a 16-byte input chunk, one packed 32-byte state record load
+//     per state and symbol.
+//   * An instance whose set outgrows kNfaK is replayed by the whole workgroup
+//     from its start: frontier lists and a visited bitset in global scratch,
+//     the matches it had already reported skipped.
+//   * Matches go to an LDS buffer keyed by (start - segment start, k), k the
+//     instance's match count so far; labels of one symbol are reported in
+//     increasing order, so k orders (end, label) within a start.  Offsets come
+//     from per-workgroup epoch-tagged count slots as in the DFA scan; a
+//     segment whose matches overflow the buffer is walked again 256 starts at
+//     a time to count, scan and write.
+#include "scan_common.h"
+
+namespace pfsmk {
+
+namespace {
+
+constexpr int NT = kNfaThreads;
+constexpr int W = kNfaWindow;
+constexpr int K = 4;  // states a queued walk keeps
+constexpr int QW = kNfaQueue * 2;
+constexpr int QK = QW / 64;
+constexpr int MC = kNfaMatchCap;
+constexpr int BC = kNfaBigCap;
+
+struct Walk {
+    int32_t start, pos, k, n;
+    uint32_t s[K];
+};
+
+struct Big {
+    int32_t start, k0, pos0, pad;
+};
+
+// Where a walk's matches go.
+enum Mode : int { kBuffer = 0, kCount = 1, kWrite = 2 };
+
+struct NfaCtx {
+    const NfaArgs &a;
+    const uint32_t *pbits_s;
+    const int32_t *f1o_s;
+    const int32_t *e1o_s;
+    uint32_t *mkey;
+    int32_t *mend;
+    int32_t *mlab;
+    int *mn;
+    int *ovf;
+    int64_t seg_lo;
+    int32_t n32;
+    long long T = 0, X = 0, L = 0, M = 0;
+
+    // Record one match of the instance started at `start`.  k is the number
+    // of matches it reported before this one.
+    __device__ __forceinline__ void put(int mode, int32_t start, int32_t end, int32_t label, int32_t k,
+                                        long long at) {
+        if (mode == kBuffer) {
+            ++M;
+            if (*ovf) return;
+            const int slot = atomicAdd(mn, 1);
+            if (slot < MC) {
+                mkey[slot] = ((uint32_t)(start - seg_lo) << 16) | (uint32_t)(k & 0xffff);
+                mend[slot] = end;
+                mlab[slot] = label;
+            } else {
+                *ovf = 1;
+            }
+        } else if (mode == kWrite) {
+            if (at + k < a.cap) {
+                MatchOut *p = &a.out[at + k];
+                p->start = start;
+                p->end = end;
+                p->label = label;
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ bool edge_matches(const NfaArgs &a, uint32_t test, int byte) {
+    const uint32_t kind = (test >> 8) & 3u;
+    if (kind == 0) return (int)(test & 255u) == byte;
+    if (kind == 1) return true;
+    return (a.class_bits[(size_t)(test >> 10) * 8 + (byte >> 5)] >> (byte & 31)) & 1u;
+}
+
+// Duplicate-free insertion of a target word into O[0..nO); false when the
+// set would exceed K.
+__device__ __forceinline__ bool set_insert(uint32_t (&O)[K], int &nO, uint32_t w) {
+    const uint32_t q = w & kStateMask;
+    bool dup = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) dup |= (j < nO) && ((O[j] & kStateMask) == q);
+    if (dup) return true;
+    if (nO >= K) return false;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j == nO) O[j] = w;
+    ++nO;
+    return true;
+}
+
+__device__ __forceinline__ bool add_target(const NfaArgs &a, uint32_t (&O)[K], int &nO, uint32_t tgt) {
+    if (!(tgt & kTgtList)) return set_insert(O, nO, tgt);
+    const int idx = (int)(tgt & ~kTgtList);
+    bool ok = true;
+    for (int j = a.cl_off[idx]; j < a.cl_off[idx + 1] && ok; ++j) ok = set_insert(O, nO, a.cl[j]);
+    return ok;
+}
+
+// One symbol for a set: O = closure(delta(S, byte)) over live states.
+// Returns false when O would exceed K states.
+__device__ __forceinline__ bool nfa_step(const NfaArgs &a, const uint32_t (&S)[K], int nS, int byte,
+                                         uint32_t (&O)[K], int &nO) {
+    nO = 0;
+    NfaRec r[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < nS) r[j] = a.rec[S[j] & kStateMask];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j < nS && ok) {
+            if (r[j].info & kRecInline) {
+                if (r[j].n_edges > 0 && edge_matches(a, r[j].e0_test, byte)) ok = add_target(a, O, nO, r[j].e0_tgt);
+                if (ok && r[j].n_edges > 1 && edge_matches(a, r[j].e1_test, byte))
+                    ok = add_target(a, O, nO, r[j].e1_tgt);
+            } else {
+                for (int e = 0; e < r[j].n_edges && ok; ++e) {
+                    const uint2 ed = reinterpret_cast<const uint2 *>(a.edges)[r[j].edge_off + e];
+                    if (edge_matches(a, ed.x, byte)) ok = add_target(a, O, nO, ed.y);
+                }
+            }
+        }
+    }
+    return ok;
+}
+
+// Report the labels of the final states of O (ascending, once each).
+__device__ __forceinline__ void emit_set(NfaCtx &c, int mode, const uint32_t (&O)[K], int nO, int32_t start,
+                                         int32_t end, int32_t &k, int32_t k0, long long at) {
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) any |= (j < nO) && (O[j] & kTgtFinal);
+    if (!any) return;
+    int lo[K], hi[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        lo[j] = hi[j] = 0;
+        if (j < nO && (O[j] & kTgtFinal)) {
+            const NfaRec &r = c.a.rec[O[j] & kStateMask];
+            lo[j] = r.lab_off;
+            hi[j] = r.lab_off + (int)(r.info >> 8);
+        }
+    }
+    int last = -1;
+    for (;;) {
+        int m = 0x7fffffff;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            while (lo[j] < hi[j] && c.a.lab[lo[j]] <= last) ++lo[j];
+            if (lo[j] < hi[j]) m = min(m, c.a.lab[lo[j]]);
+        }
+        if (m == 0x7fffffff) break;
+        if (k >= k0) c.put(mode, start, end, m, k, at);
+        ++k;
+        last = m;
+    }
+}
+
+// Report a sorted unique label list.
+__device__ __forceinline__ void emit_list(NfaCtx &c, int mode, const int32_t *lab, int lo, int hi, int32_t start,
+                                          int32_t end, int32_t &k, int32_t k0, long long at) {
+    for (int l = lo; l < hi; ++l, ++k)
+        if (k >= k0) c.put(mode, start, end, lab[l], k, at);
+}
+
+// Sets after the first two symbols of start i (when i + 1 < n).  Returns the
+// number of states in the second set, or -1 when it exceeds K (S untouched).
+__device__ __forceinline__ int first_two(NfaCtx &c, int c1, int c2, uint32_t (&S)[K], int &pair_lab_lo,
+                                         int &pair_lab_hi, bool &overflow) {
+    const NfaArgs &a = c.a;
+    overflow = false;
+    pair_lab_lo = pair_lab_hi = 0;
+    int nS = 0;
+    if (a.pair_on) {
+        const int p = c1 * 256 + c2;
+        if (!((c.pbits_s[p >> 5] >> (p & 31)) & 1u)) return 0;
+        const int s_lo = a.p_off[p], s_hi = a.p_off[p + 1];
+        pair_lab_lo = a.pl_off[p];
+        pair_lab_hi = a.pl_off[p + 1];
+        const int cnt = s_hi - s_lo;
+        if (cnt > K) {
+            overflow = true;
+            return cnt;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < cnt) S[j] = a.p_st[s_lo + j];
+        return cnt;
+    }
+    // No pair cache: expand the first-symbol set directly.
+    for (int j = c.f1o_s[c1]; j < c.f1o_s[c1 + 1]; ++j) {
+        const NfaRec r = a.rec[a.f1[j] & kStateMask];
+        bool ok = true;
+        if (r.info & kRecInline) {
+            if (r.n_edges > 0 && edge_matches(a, r.e0_test, c2)) ok = add_target(a, S, nS, r.e0_tgt);
+            if (ok && r.n_edges > 1 && edge_matches(a, r.e1_test, c2)) ok = add_target(a, S, nS, r.e1_tgt);
+        } else {
+            for (int e = 0; e < r.n_edges && ok; ++e) {
+                const uint2 ed = reinterpret_cast<const uint2 *>(a.edges)[r.edge_off + e];
+                if (edge_matches(a, ed.x, c2)) ok = add_target(a, S, nS, ed.y);
+            }
+        }
+        if (!ok) {
+            overflow = true;
+            return K + 1;
+        }
+    }
+    return nS;
+}
+
+// The labels reported after the second symbol when there is no pair cache
+// (finals among S); with the cache they come from the pair's label list.
+//
+// Full walk of one start by one lane, for the count and write passes of a
+// dense segment.  Returns the number of matches, or -1 when a set outgrows K
+// (the caller replays that start with the whole workgroup).
+__device__ long long walk_lane(NfaCtx &c, int32_t i, int mode, long long at) {
+    const NfaArgs &a = c.a;
+    int32_t k = 0;
+    const int c1 = a.x[i];
+    const int n1 = c.f1o_s[c1 + 1] - c.f1o_s[c1];
+    if (n1 == 0) return 0;
+    emit_list(c, mode, a.e1, c.e1o_s[c1], c.e1o_s[c1 + 1], i, i, k, 0, at);
+    if (i + 1 >= c.n32) return k;
+    uint32_t S[K];
+    int llo, lhi;
+    bool ovf;
+    int nS = first_two(c, c1, a.x[i + 1], S, llo, lhi, ovf);
+    if (ovf) return -1;
+    if (a.pair_on) emit_list(c, mode, a.p_lab, llo, lhi, i, i + 1, k, 0, at);
+    else emit_set(c, mode, S, nS, i, i + 1, k, 0, at);
+    int32_t pos = i + 2;
+    while (nS > 0 && pos < c.n32) {
+        uint32_t O[K];
+        int nO;
+        if (!nfa_step(a, S, nS, a.x[pos], O, nO)) return -1;
+        emit_set(c, mode, O, nO, i, pos, k, 0, at);
+#pragma unroll
+        for (int j = 0; j < K; ++j) S[j] = O[j];
+        nS = nO;
+        ++pos;
+    }
+    return k;
+}
+
+__device__ __forceinline__ int block_min(int v, int *redi) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    if (lane_id() == 0) redi[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int m = redi[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) m = min(m, redi[i]);
+    __syncthreads();
+    return m;
+}
+
+// Replay of start s by the whole workgroup with unbounded sets: frontier
+// lists in global scratch, duplicates removed with a visited bitset that is
+// cleared again after every symbol.  Matches before the k0-th are skipped
+// (already reported); work counters are kept for positions >= pos0 (earlier
+// ones were counted).  Returns the number of matches reported from k0 on
+// (every thread).
+__device__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0, int32_t pos0, int mode, long long at,
+                                uint32_t *F0, uint32_t *F1, uint32_t *bits, int *sh) {
+    // sh[0]: next frontier size, sh[1..NT/64]: reduction slots, sh[8]: k
+    const NfaArgs &a = c.a;
+    const int tid = threadIdx.x;
+    const int c1 = a.x[s];
+    int nF = c.f1o_s[c1 + 1] - c.f1o_s[c1];
+    for (int j = tid; j < nF; j += NT) F0[j] = a.f1[c.f1o_s[c1] + j];
+    int32_t k = 0;  // tracked by every thread identically
+    if (tid == 0) {
+        if (s >= pos0) {
+            ++c.T;
+            c.X += nF;
+        }
+        emit_list(c, mode, a.e1, c.e1o_s[c1], c.e1o_s[c1 + 1], s, s, k, k0, at);
+    } else {
+        k += c.e1o_s[c1 + 1] - c.e1o_s[c1];
+    }
+    if (tid == 0) sh[0] = 0;
+    __syncthreads();
+    uint32_t *cur = F0, *nxt = F1;
+    int32_t pos = s + 1;
+    while (nF > 0 && pos < c.n32) {
+        const int byte = a.x[pos];
+        for (int j = tid; j < nF; j += NT) {
+            const NfaRec r = a.rec[cur[j] & kStateMask];
+            const int ne = r.n_edges;
+            for (int e = 0; e < ne; ++e) {
+                uint32_t test, tgt;
+                if (r.info & kRecInline) {
+                    test = e == 0 ? r.e0_test : r.e1_test;
+                    tgt = e == 0 ? r.e0_tgt : r.e1_tgt;
+                } else {
+                    const uint2 ed = reinterpret_cast<const uint2 *>(a.edges)[r.edge_off + e];
+                    test = ed.x;
+                    tgt = ed.y;
+                }
+                if (!edge_matches(a, test, byte)) continue;
+                int lo = 0, hi = 1;
+                if (tgt & kTgtList) {
+                    const int idx = (int)(tgt & ~kTgtList);
+                    lo = a.cl_off[idx];
+                    hi = a.cl_off[idx + 1];
+                }
+                for (int t = lo; t < hi; ++t) {
+                    const uint32_t w = (tgt & kTgtList) ? a.cl[t] : tgt;
+                    const uint32_t q = w & kStateMask;
+                    const uint32_t bit = 1u << (q & 31);
+                    const uint32_t old = atomicOr(&bits[q >> 5], bit);
+                    if (!(old & bit)) nxt[atomicAdd(&sh[0], 1)] = w;
+                }
+            }
+        }
+        __syncthreads();
+        const int nN = sh[0];
+        __syncthreads();
+        for (int j = tid; j < nN; j += NT) {
+            const uint32_t q = nxt[j] & kStateMask;
+            atomicAnd(&bits[q >> 5], ~(1u << (q & 31)));
+        }
+        if (tid == 0) {
+            sh[0] = 0;
+            if (pos >= pos0) {
+                ++c.T;
+                c.X += nN;
+            }
+        }
+        // labels of the final states, ascending, once each
+        int last = -1;
+        for (;;) {
+            int mine = 0x7fffffff;
+            for (int j = tid; j < nN; j += NT) {
+                if (!(nxt[j] & kTgtFinal)) continue;
+                const NfaRec r = a.rec[nxt[j] & kStateMask];
+                const int hi = r.lab_off + (int)(r.info >> 8);
+                for (int l = r.lab_off; l < hi; ++l) {
+                    const int v = a.lab[l];
+                    if (v > last) {
+                        mine = min(mine, v);
+                        break;
+                    }
+                }
+            }
+            const int m = block_min(mine, sh + 1);
+            if (m == 0x7fffffff) break;
+            if (tid == 0 && k >= k0) c.put(mode, s, pos, m, k, at);
+            ++k;
+            last = m;
+        }
+        uint32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        nF = nN;
+        ++pos;
+        __syncthreads();
+    }
+    return (long long)k - k0;
+}
+
+// One queue round of this wave: every walk advances through the rest of the
+// 16-byte chunk holding its next position.  Walks whose set outgrows K go to
+// the workgroup's replay list.
+__device__ __forceinline__ void drain_round(NfaCtx &c, Walk *q, int &qcount, Big *big_s, int *nbig) {
+    const NfaArgs &a = c.a;
+    const int lane = lane_id();
+    Walk e[QK];
+    bool alive[QK];
+#pragma unroll
+    for (int j = 0; j < QK; ++j) {
+        const int idx = lane + 64 * j;
+        alive[j] = idx < qcount;
+        if (alive[j]) e[j] = q[idx];
+        else e[j].n = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < QK; ++j) {
+        if (!alive[j]) continue;
+        const int64_t c0 = (int64_t)(e[j].pos & ~15);
+        const uint4 ch = load_granule(a.x, c0);
+        ++c.L;
+        const int steps = (int)((c0 + 16 < a.n ? c0 + 16 : a.n) - e[j].pos);
+        for (int st = 0; st < steps && alive[j]; ++st) {
+            uint32_t O[K];
+            int nO;
+            if (!nfa_step(a, e[j].s, e[j].n, byte_of(ch, e[j].pos & 15), O, nO)) {
+                const int slot = atomicAdd(nbig, 1);
+                if (slot < BC) big_s[slot] = Big{e[j].start, e[j].k, e[j].pos, 0};
+                alive[j] = false;
+                break;
+            }
+            ++c.T;
+            c.X += nO;
+            emit_set(c, kBuffer, O, nO, e[j].start, e[j].pos, e[j].k, 0, 0);
+#pragma unroll
+            for (int t = 0; t < K; ++t) e[j].s[t] = O[t];
+            e[j].n = nO;
+            ++e[j].pos;
+            if (nO == 0) alive[j] = false;
+        }
+    }
+    int nc = 0;
+#pragma unroll
+    for (int j = 0; j < QK; ++j) {
+        const bool keep = alive[j] && e[j].n > 0 && e[j].pos < c.n32;
+        const int slot = wave_push_slot(nc, keep);
+        if (keep) q[slot] = e[j];
+    }
+    __builtin_amdgcn_wave_barrier();
+    qcount = nc;
+}
+
+__global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
+    __shared__ uint32_t pbits_s[2048];
+    __shared__ int32_t f1o_s[257];
+    __shared__ int32_t e1o_s[257];
+    __shared__ Walk qall[(NT / 64) * QW];
+    __shared__ uint32_t mkey[MC];
+    __shared__ int32_t mend[MC];
+    __shared__ int32_t mlab[MC];
+    __shared__ Big big_s[BC];
+    __shared__ int mn, ovf, nbig;
+    __shared__ int sh[16];
+    __shared__ long long red[NT / 64];
+    __shared__ long long red4[4 * (NT / 64)];
+    __shared__ unsigned epoch_s;
+
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6;
+    const int b = blockIdx.x;
+    const int32_t n32 = (int32_t)a.n;
+    if (a.pair_on)
+        for (int i = tid; i < 2048; i += NT) pbits_s[i] = a.p_bits[i];
+    for (int i = tid; i < 257; i += NT) {
+        f1o_s[i] = a.f1_off[i];
+        e1o_s[i] = a.e1_off[i];
+    }
+    if (tid == 0) {
+        mn = 0;
+        ovf = 0;
+        nbig = 0;
+        epoch_s = first_epoch(a.slots, b);
+    }
+    __syncthreads();
+    const unsigned epoch0 = epoch_s;
+    const size_t ns = (size_t)a.n_states;
+    uint32_t *F0 = a.big_front + (size_t)b * 2 * ns;
+    uint32_t *F1 = F0 + ns;
+    uint32_t *bits = a.big_bits + (size_t)b * ((ns + 31) / 32);
+
+    NfaCtx c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf, 0, n32};
+    Walk *q = qall + wv * QW;
+    long long base_out = 0;
+
+    // Replay every listed start with the whole workgroup.
+    auto run_big = [&]() __attribute__((always_inline)) {
+        __syncthreads();
+        const int nb = min(nbig, BC);
+        __syncthreads();
+        for (int j = 0; j < nb; ++j) {
+            const Big bg = big_s[j];
+            walk_block(c, bg.start, bg.k0, bg.pos0, kBuffer, 0, F0, F1, bits, sh);
+        }
+        __syncthreads();
+        if (tid == 0) nbig = 0;
+        __syncthreads();
+    };
+
+    for (int r = 0; r < a.n_rounds; ++r) {
+        const int64_t seg_lo = ((int64_t)r * a.n_blocks + b) * a.seg;
+        const int64_t seg_hi = seg_lo + a.seg < a.n ? seg_lo + a.seg : a.n;
+        c.seg_lo = seg_lo;
+        const long long m_before = c.M;
+        int qcount = 0;
+        for (int64_t wbase = seg_lo; wbase < seg_hi; wbase += W) {
+            const int64_t wend = wbase + W < seg_hi ? wbase + W : seg_hi;
+            const int64_t i0 = wbase + 16 * tid;
+            const uint4 mine = i0 < a.n ? load_granule(a.x, i0) : make_uint4(0, 0, 0, 0);
+            const int64_t nv64 = wend - i0;
+            const int nvalid = nv64 <= 0 ? 0 : (nv64 >= 16 ? 16 : (int)nv64);
+            const int tail = (nvalid == 16 && i0 + 16 < a.n) ? a.x[i0 + 16] : 0;
+            for (int k = 0; k < 16; ++k) {
+                bool push = false;
+                Walk ent;
+                ent.n = 0;
+                if (k < nvalid) {
+                    const int32_t i = (int32_t)(i0 + k);
+                    const int c1 = byte_of(mine, k);
+                    ++c.T;
+                    const int n1 = f1o_s[c1 + 1] - f1o_s[c1];
+                    if (n1 > 0) {
+                        c.X += n1;
+                        int32_t km = 0;
+                        emit_list(c, kBuffer, a.e1, e1o_s[c1], e1o_s[c1 + 1], i, i, km, 0, 0);
+                        if (i + 1 < n32) {
+                            const int c2 = k < 15 ? byte_of(mine, k + 1) : tail;
+                            int llo, lhi;
+                            bool over;
+                            const int nS = first_two(c, c1, c2, ent.s, llo, lhi, over);
+                            if (over) {
+                                const int slot = atomicAdd(&nbig, 1);
+                                if (slot < BC) big_s[slot] = Big{i, km, i + 1, 0};
+                            } else {
+                                ++c.T;
+                                c.X += nS;
+                                if (a.pair_on) emit_list(c, kBuffer, a.p_lab, llo, lhi, i, i + 1, km, 0, 0);
+                                else emit_set(c, kBuffer, ent.s, nS, i, i + 1, km, 0, 0);
+                                if (nS > 0 && i + 2 < n32) {
+                                    push = true;
+                                    ent.start = i;
+                                    ent.pos = i + 2;
+                                    ent.k = km;
+                                    ent.n = nS;
+                                }
+                            }
+                        }
+                    }
+                }
+                const int slot = wave_push_slot(qcount, push);
+                if (push) q[slot] = ent;
+                while (qcount > QW - 64) drain_round(c, q, qcount, big_s, &nbig);
+            }
+            // replay list getting full: run it now (uniform decision)
+            __syncthreads();
+            const int pending = nbig;
+            __syncthreads();
+            if (pending > BC / 2) {
+                while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig);
+                run_big();
+            }
+        }
+        while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig);
+        __syncthreads();
+        if (nbig > BC) {
+            // more starts overflowed than the list holds: the whole segment
+            // is rebuilt below from per-start walks
+            if (tid == 0) ovf = 1;
+        }
+        __syncthreads();
+        if (!ovf) run_big();
+
+        // Offsets: this round's count, the peers' counts, placement.
+        const long long mine_m = block_sum<NT>(c.M - m_before, red);
+        long long round_total;
+        const long long excl =
+            grid_prefix<NT>(a.slots, a.n_blocks, b, (epoch0 + r) & kEpochMask, mine_m, red, &round_total);
+        const long long at0 = base_out + excl;
+        if (!ovf) {
+            const int m = mn;
+            for (int e = tid; e < m; e += NT) {
+                const uint32_t mk = mkey[e];
+                int rank = 0;
+                int j = 0;
+                for (; j + 16 <= m; j += 16) {
+                    const uint4 k0 = *reinterpret_cast<const uint4 *>(mkey + j);
+                    const uint4 k1 = *reinterpret_cast<const uint4 *>(mkey + j + 4);
+                    const uint4 k2 = *reinterpret_cast<const uint4 *>(mkey + j + 8);
+                    const uint4 k3 = *reinterpret_cast<const uint4 *>(mkey + j + 12);
+                    rank += (k0.x < mk) + (k0.y < mk) + (k0.z < mk) + (k0.w < mk);
+                    rank += (k1.x < mk) + (k1.y < mk) + (k1.z < mk) + (k1.w < mk);
+                    rank += (k2.x < mk) + (k2.y < mk) + (k2.z < mk) + (k2.w < mk);
+                    rank += (k3.x < mk) + (k3.y < mk) + (k3.z < mk) + (k3.w < mk);
+                }
+                for (; j < m; ++j) rank += mkey[j] < mk;
+                const long long at = at0 + rank;
+                if (at < a.cap) {
+                    MatchOut *p = &a.out[at];
+                    p->start = (int32_t)(seg_lo + (mk >> 16));
+                    p->end = mend[e];
+                    p->label = mlab[e];
+                }
+            }
+        } else {
+            // Dense segment: count, scan and write 256 starts at a time.
+            long long run = at0;
+            for (int64_t c0 = seg_lo; c0 < seg_hi; c0 += NT) {
+                const int64_t i = c0 + tid;
+                const bool own = i < seg_hi;
+                long long cnt = own ? walk_lane(c, (int32_t)i, kCount, 0) : 0;
+                // starts whose sets outgrow K: counted by the whole workgroup
+                for (;;) {
+                    const int want = block_min(cnt < 0 ? tid : 0x7fffffff, sh + 1);
+                    if (want == 0x7fffffff) break;
+                    const long long v =
+                        walk_block(c, (int32_t)(c0 + want), 0, 0x7fffffff, kCount, 0, F0, F1, bits, sh);
+                    if (tid == want) cnt = v;
+                    __syncthreads();
+                }
+                long long ctot;
+                const long long ex = block_excl_scan<NT>(cnt, red, &ctot);
+                const long long lane_cnt = own && cnt > 0 ? walk_lane(c, (int32_t)i, kWrite, run + ex) : 0;
+                bool pend = lane_cnt < 0;
+                for (;;) {
+                    const int want = block_min(pend ? tid : 0x7fffffff, sh + 1);
+                    if (want == 0x7fffffff) break;
+                    if (tid == want) red[0] = run + ex;
+                    __syncthreads();
+                    const long long base = red[0];
+                    __syncthreads();
+                    walk_block(c, (int32_t)(c0 + want), 0, 0x7fffffff, kWrite, base, F0, F1, bits, sh);
+                    if (tid == want) pend = false;
+                }
+                __syncthreads();
+                run += ctot;
+            }
+        }
+        base_out += round_total;
+        __syncthreads();
+        if (tid == 0) {
+            mn = 0;
+            ovf = 0;
+            nbig = 0;
+        }
+        __syncthreads();
+    }
+    if (b == 0 && tid == 0) *a.total = base_out;
+    long long st4[4] = {c.T, c.X, c.L, c.M};
+    block_sum4<NT>(st4, red4);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.bstats[4 * b + k] = st4[k];
+    }
+}
+
+}  // namespace
+
+const void *nfa_kernel_fn() { return reinterpret_cast<const void *>(&nfa_scan_kernel); }
+
+}  // namespace pfsmk

@@ -81,3 +81,73 @@ const void *dfa_kernel_fn(int enc, bool identity_map);
 hipError_t launch_write_zero(int64_t *p, hipStream_t stream);
 
 }  // namespace pfsmk
+
+// ---------------------------------------------------------------- NFA scan
+
+namespace pfsmk {
+
+constexpr int kNfaThreads = 256;             // workgroup: 4 wave64
+constexpr int kNfaWindow = kNfaThreads * 16; // 16 starts per thread
+constexpr int kNfaSegMax = 65536;            // bytes per workgroup and round
+constexpr int kNfaK = 8;                     // states a lane keeps for one walk
+constexpr int kNfaQueue = 64;                // walk queue entries per wave
+constexpr int kNfaMatchCap = 1024;           // LDS match buffer per workgroup
+constexpr int kNfaBigCap = 256;              // replayed starts listed per workgroup
+constexpr int kNfaLabelsMax = 1 << 24;       // labels per state
+
+// Packed state record, one 32-byte load per state and step.  Only live
+// targets are kept (a state is live when a final state with an enabled label
+// is reachable from it): the instance drops the others at once anyway.
+//   info: bit 0 live, bit 1 final, bit 2 edges inline, bits 8.. label count
+//   edge test word: bits 0-7 byte, bits 8-9 kind (0 one byte, 1 any byte,
+//     2 class bitmap), bits 10-31 class id
+//   edge target word: bit 31 clear: a state whose epsilon closure is itself,
+//     bit 31 set: index of its closure list; bit 30: the state is final
+struct __attribute__((aligned(16))) NfaRec {
+    uint32_t info;
+    int32_t lab_off;
+    int32_t edge_off;  // into the edge array when not inline
+    int32_t n_edges;
+    uint32_t e0_test, e0_tgt, e1_test, e1_tgt;
+};
+constexpr uint32_t kRecLive = 1, kRecFinal = 2, kRecInline = 4;
+constexpr uint32_t kTgtList = 1u << 31, kTgtFinal = 1u << 30, kStateMask = (1u << 30) - 1;
+
+struct NfaArgs {
+    const uint8_t *x;  // 16-byte aligned
+    int64_t n;
+    int32_t n_states;
+    const NfaRec *rec;          // [n_states]
+    const uint32_t *edges;      // (test, target) pairs for records with more than two edges
+    const uint32_t *class_bits; // [n_classes * 8]
+    const int32_t *cl_off;      // closure lists: [n_lists + 1]
+    const uint32_t *cl;         // target words
+    const int32_t *lab;         // enabled labels, sorted and unique per state
+    // first symbol: closure(delta(closure({q0}), c)) restricted to live states
+    const int32_t *f1_off;      // [257]
+    const uint32_t *f1;         // target words
+    const int32_t *e1_off;      // [257] labels reported after the first symbol
+    const int32_t *e1;
+    // first two symbols (when pair_on): the same for the byte pair (c1, c2)
+    int32_t pair_on;
+    const uint32_t *p_bits;     // [2048] pair has states or labels
+    const int32_t *p_off;       // [65537]
+    const uint32_t *p_st;
+    const int32_t *pl_off;      // [65537]
+    const int32_t *p_lab;
+    MatchOut *out;
+    int64_t cap;
+    int64_t *total;
+    unsigned long long *slots;  // [n_blocks]
+    long long *bstats;          // [n_blocks * 4]
+    int64_t seg;
+    int32_t n_blocks, n_rounds;
+    // per-workgroup replay scratch: two frontiers of n_states entries and a
+    // bitset of n_states bits (all clear between uses)
+    uint32_t *big_front;        // [n_blocks * 2 * n_states]
+    uint32_t *big_bits;         // [n_blocks * ((n_states + 31) / 32)]
+};
+
+const void *nfa_kernel_fn();
+
+}  // namespace pfsmk
