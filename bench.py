@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--latency-iters", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing (counter calibration)")
     return ap.parse_args()
 
 
@@ -83,6 +85,13 @@ def main():
     out = torch.empty((cap, 3), dtype=torch.int32, device=dev)
     counts = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.calib_copy_mib:
+        a_ = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        b_ = torch.empty_like(a_)
+        b_.copy_(a_)
+        torch.cuda.synchronize()
+        del a_, b_
 
     # reference count and work counters of one scan (from the kernel's own counters)
     n_ref, _ = P.pfsm_scan(h, xs[0], out=out)

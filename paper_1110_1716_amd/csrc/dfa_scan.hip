@@ -1,12 +1,12 @@
 // All-matches DFA scan for gfx950 (Section III.B with a deterministic
 // transition function; the DFA case of Section III.C).
 //
-// Persistent cooperative grid of 1024-thread workgroups (16 wave64, one per
+// Persistent cooperative grid of 768-thread workgroups (12 wave64, one per
 // compute unit when the table is resident in LDS).  Workgroup b owns the
 // start positions of one contiguous segment per round (lazy data
 // partitioning, Section III.D.2: a segment owns its starts, its walks read
-// past its end until they die).  The segment is processed in 16 KiB windows:
-//   1. the window is staged from HBM into LDS with 16-byte loads issued two
+// past its end until they die).  The segment is processed in windows of 16 bytes per thread:
+//   1. the window (12 KiB) is staged from HBM into LDS with 16-byte loads issued two
 //      windows ahead;
 //   2. every start takes its first symbol through the row of q0 cached in LDS
 //      by byte (Section III.B steps 1-4 for the fresh tag), 16 independent
@@ -23,7 +23,7 @@
 // At the end of a round each workgroup publishes its match count in its own
 // epoch-tagged slot and sums its peers' slots (no shared counters), then
 // writes every buffered match at its rank.  A segment whose matches do not
-// fit the buffer is re-walked 1024 starts at a time: count, scan, write.
+// fit the buffer is re-walked 768 starts at a time: count, scan, write.
 #include "scan_common.h"
 
 namespace pfsmk {
@@ -107,22 +107,26 @@ struct DfaCtx {
         if constexpr (kResident) return lab_s[l];
         else return a.lab[l];
     }
-    // Report every label of s for the instance started at `start`.
+    // Report every label of s for the instance started at `start`; k counts
+    // the instance's reports (ordering key within a start).
     __device__ __forceinline__ void emit(int32_t start, int32_t end, int s, int32_t &k) {
-        const int lo = lab_lo(s), hi = lab_lo(s + 1);
-        M += hi - lo;
-        for (int l = lo; l < hi; ++l, ++k) {
-            if (*ovf) continue;
-            const int slot = atomicAdd(mn, 1);
-            if (slot < MC) {
-                mkey[slot] = ((uint32_t)(start - seg_lo) << 16) | (uint32_t)(k & 0xffff);
-                mend[slot] = end;
-                mlab[slot] = lab_at(l);
+        const int lo = lab_lo(s), cnt = lab_lo(s + 1) - lo;
+        M += cnt;
+        if (!*ovf) {
+            const int slot = atomicAdd(mn, cnt);
+            if (slot + cnt <= MC) {
+                for (int l = 0; l < cnt; ++l) {
+                    mkey[slot + l] = ((uint32_t)(start - seg_lo) << 16) | (uint32_t)((k + l) & 0xffff);
+                    mend[slot + l] = end;
+                    mlab[slot + l] = lab_at(lo + l);
+                }
             } else {
                 *ovf = 1;
             }
         }
+        k += cnt;
     }
+    __device__ __forceinline__ int n_labels(int s) const { return lab_lo(s + 1) - lab_lo(s); }
     // The 16-byte chunk holding position p (p is a multiple of 16).
     __device__ __forceinline__ uint4 chunk(int64_t p) {
         const int64_t r = p - wbase;
@@ -244,6 +248,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     uint8_t *tab_s = lds + a.off_tab;
     QEnt *qall = reinterpret_cast<QEnt *>(lds + a.off_q);
     uint32_t *mkey = reinterpret_cast<uint32_t *>(lds + a.off_m);
+    uint16_t *list_all = reinterpret_cast<uint16_t *>(lds + a.off_list);
     int32_t *mend = reinterpret_cast<int32_t *>(mkey + MC);
     int32_t *mlab = mend + MC;
     __shared__ int mn, ovf;
@@ -344,53 +349,60 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         c.wbase = wbase;
         c.staged = staged;
 
-        // First symbol of the 16 starts owned by this thread.
+        // Symbol one for the 16 starts owned by this thread: 16 independent
+        // lookups of the q0 row, giving the mask of live instances.
         const int il0 = 16 * tid;
         const int64_t i0 = wbase + il0;
         const int64_t nv64 = wend - i0;
         const int nvalid = nv64 <= 0 ? 0 : (nv64 >= 16 ? 16 : (int)nv64);
-        // byte after this thread's 16 (the next window's first byte for the
-        // last thread)
-        const int tail = (nvalid == 16 && i0 + 16 < a.n) ? (il0 + 16 < staged ? xs[il0 + 16] : a.x[i0 + 16]) : 0;
-        unsigned live_mask = 0;
+        unsigned lm = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            if (k < nvalid && first_s[byte_of(mine, k)] >= 0) live_mask |= 1u << k;
+            if (k < nvalid && first_s[byte_of(mine, k)] >= 0) lm |= 1u << k;
         c.T += nvalid;
-        c.X += __popc(live_mask);
-        // Second symbol of the live ones, one per lane per pass so the queue
-        // pushes stay wave-uniform.
-        for (;;) {
-            const bool more = __any(live_mask != 0);
-            if (!more) break;
+        c.X += __popc(lm);
+        // Compact the wave's live instances into its LDS list (prefix sum of
+        // the lanes' counts), then advance them with every lane busy.
+        const int cnt = __popc(lm);
+        const int incl = (int)wave_incl_scan(cnt);
+        const int total = __shfl(incl, 63);
+        int off = incl - cnt;
+        uint16_t *lst = list_all + wv * (64 * 16);
+        while (lm) {
+            const int k = __ffs(lm) - 1;
+            lm &= lm - 1;
+            lst[off++] = (uint16_t)(il0 + k);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int e0 = 0; e0 < total; e0 += 64) {
+            const int e = e0 + lane_id();
             bool push = false;
             QEnt ent{0, 0, 0, 0};
-            if (live_mask) {
-                const int k = __ffs(live_mask) - 1;
-                live_mask &= live_mask - 1;
-                const int b0 = byte_of(mine, k);
-                const int b1 = k < 15 ? byte_of(mine, k + 1) : tail;
-                const int32_t i = (int32_t)(i0 + k);
+            if (e < total) {
+                const int il = lst[e];
+                const int32_t i = (int32_t)(wbase + il);
+                const int b0 = xs[il];
                 const int s1 = first_s[b0];
                 int32_t km = 0;
                 if (c.flag(s1) & kFinal) c.emit(i, i, s1, km);
                 if (i + 1 < n32) {
                     ++c.T;
+                    const int b1 = il + 1 < staged ? xs[il + 1] : a.x[i + 1];
                     const int sy = c.sym(b1);
-                    const int s2 = sy < 0 ? -1 : c.live(c.tab2(b0, s1, sy));
-                    if (s2 >= 0) {
+                    const int t2 = sy < 0 ? -1 : c.live(c.tab2(b0, s1, sy));
+                    if (t2 >= 0) {
                         ++c.X;
-                        if (c.flag(s2) & kFinal) c.emit(i, i + 1, s2, km);
+                        if (c.flag(t2) & kFinal) c.emit(i, i + 1, t2, km);
                         if (i + 2 < n32) {
                             push = true;
-                            ent = QEnt{i, s2, i + 2, km};
+                            ent = QEnt{i, t2, i + 2, km};
                         }
                     }
                 }
             }
+            while (qcount > QW - 64) drain_round(c, q, qcount);
             const int slot = wave_push_slot(qcount, push);
             if (push) q[slot] = ent;
-            while (qcount > QW - 64) drain_round(c, q, qcount);
         }
     };
 
@@ -415,28 +427,56 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             grid_prefix<NT>(a.slots, a.n_blocks, b, (epoch0 + r) & kEpochMask, mine_m, red, &round_total);
         const long long at0 = base_out + excl;
         if (!ovf) {
+            // Rank of every buffered match in (start, end, label) order:
+            // bucket by start offset / 64 (histogram, scan, scatter), then
+            // compare within the bucket.  The queue area is free here.
             const int m = mn;
-            if (tid < m) {
-                const uint32_t mk = mkey[tid];
-                int rank = 0;
-                int k = 0;
-                for (; k + 16 <= m; k += 16) {
-                    const uint4 k0 = *reinterpret_cast<const uint4 *>(mkey + k);
-                    const uint4 k1 = *reinterpret_cast<const uint4 *>(mkey + k + 4);
-                    const uint4 k2 = *reinterpret_cast<const uint4 *>(mkey + k + 8);
-                    const uint4 k3 = *reinterpret_cast<const uint4 *>(mkey + k + 12);
-                    rank += (k0.x < mk) + (k0.y < mk) + (k0.z < mk) + (k0.w < mk);
-                    rank += (k1.x < mk) + (k1.y < mk) + (k1.z < mk) + (k1.w < mk);
-                    rank += (k2.x < mk) + (k2.y < mk) + (k2.z < mk) + (k2.w < mk);
-                    rank += (k3.x < mk) + (k3.y < mk) + (k3.z < mk) + (k3.w < mk);
+            int *hist = reinterpret_cast<int *>(qall);
+            int *base = hist + 1024;
+            int *fill = base + 1024;
+            int *memb = fill + 1024;
+            for (int j = tid; j < 1024; j += NT) {
+                hist[j] = 0;
+                fill[j] = 0;
+            }
+            __syncthreads();
+            for (int e = tid; e < m; e += NT) atomicAdd(&hist[mkey[e] >> 22], 1);
+            __syncthreads();
+            int h4[4] = {0, 0, 0, 0};
+            long long own = 0;
+            if (tid < 256) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    h4[j] = hist[4 * tid + j];
+                    own += h4[j];
                 }
-                for (; k < m; ++k) rank += mkey[k] < mk;
+            }
+            long long all_m;
+            long long run = block_excl_scan<NT>(own, red, &all_m);
+            if (tid < 256) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    base[4 * tid + j] = (int)run;
+                    run += h4[j];
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < m; e += NT) {
+                const int bk = mkey[e] >> 22;
+                memb[base[bk] + atomicAdd(&fill[bk], 1)] = e;
+            }
+            __syncthreads();
+            for (int e = tid; e < m; e += NT) {
+                const uint32_t mk = mkey[e];
+                const int bk = mk >> 22;
+                int rank = base[bk];
+                for (int j = base[bk]; j < base[bk] + hist[bk]; ++j) rank += mkey[memb[j]] < mk;
                 const long long at = at0 + rank;
                 if (at < a.cap) {
                     MatchOut *p = &a.out[at];
                     p->start = (int32_t)(seg_lo + (mk >> 16));
-                    p->end = mend[tid];
-                    p->label = mlab[tid];
+                    p->end = mend[e];
+                    p->label = mlab[e];
                 }
             }
         } else {

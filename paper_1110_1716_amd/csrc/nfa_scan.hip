@@ -241,7 +241,7 @@ __device__ __forceinline__ int first_two(NfaCtx &c, int c1, int c2, uint32_t (&S
 // Full walk of one start by one lane, for the count and write passes of a
 // dense segment.  Returns the number of matches, or -1 when a set outgrows K
 // (the caller replays that start with the whole workgroup).
-__device__ long long walk_lane(NfaCtx &c, int32_t i, int mode, long long at) {
+__device__ __forceinline__ long long walk_lane(NfaCtx &c, int32_t i, int mode, long long at) {
     const NfaArgs &a = c.a;
     int32_t k = 0;
     const int c1 = a.x[i];
@@ -288,7 +288,7 @@ __device__ __forceinline__ int block_min(int v, int *redi) {
 // (already reported); work counters are kept for positions >= pos0 (earlier
 // ones were counted).  Returns the number of matches reported from k0 on
 // (every thread).
-__device__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0, int32_t pos0, int mode, long long at,
+__device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0, int32_t pos0, int mode, long long at,
                                 uint32_t *F0, uint32_t *F1, uint32_t *bits, int *sh) {
     // sh[0]: next frontier size, sh[1..NT/64]: reduction slots, sh[8]: k
     const NfaArgs &a = c.a;

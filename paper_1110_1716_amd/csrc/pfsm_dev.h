@@ -25,7 +25,7 @@ struct MatchOut {
 
 // ---------------------------------------------------------------- DFA scan
 
-constexpr int kDfaThreads = 1024;              // one workgroup, 16 wave64
+constexpr int kDfaThreads = 768;               // one workgroup, 12 wave64
 constexpr int kDfaWindow = kDfaThreads * 16;   // 16 bytes per thread
 constexpr int kDfaSegMax = 65536;              // bytes per workgroup and round
 constexpr int kDfaQueue = 128;                 // LDS queue entries per wave
@@ -70,7 +70,7 @@ struct DfaArgs {
     int32_t n_blocks;           // persistent grid size
     int32_t n_rounds;
     // dynamic LDS layout, byte offsets
-    int32_t off_flags, off_laboff, off_lab, off_tab, off_q, off_m, lds_bytes;
+    int32_t off_flags, off_laboff, off_lab, off_tab, off_q, off_m, off_list, lds_bytes;
 };
 
 // Fixed part of the DFA kernel's dynamic LDS (window, q0 row, slots, map).

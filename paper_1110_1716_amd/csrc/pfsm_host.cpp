@@ -48,7 +48,8 @@ struct pfsm {
     bool tbl16 = true;
     int enc = kCold16;
     int32_t res_bytes = 0, n_hot = 0;
-    int32_t off_flags = 0, off_laboff = 0, off_lab = 0, off_tab = 0, off_q = 0, off_m = 0, lds_bytes = 0;
+    int32_t off_flags = 0, off_laboff = 0, off_lab = 0, off_tab = 0, off_q = 0, off_m = 0, off_list = 0,
+            lds_bytes = 0;
     int n_blocks = 0;
     const void *kernel = nullptr;
     // ---- NFA
@@ -153,7 +154,8 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
         }
         off = align16(off + (tab_bytes + 15) / 16 * 16 + 16);
         off += (kDfaThreads / 64) * kDfaQueue * 16;
-        return off + kDfaMatchCap * 12;
+        off += kDfaMatchCap * 12;
+        return off + kDfaThreads * 16 * 2;
     };
     const int64_t bytes8 = ns, bytes8d = ((ns + 3) & ~3ll) + (ns + 31) / 32 * 4, bytes16 = ns * 2;
     if (N <= 255 && bytes8 <= kDfaTableBudget && lds_total(bytes8, true) <= kDfaLdsLimit) {
@@ -213,7 +215,8 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     h->off_tab = align16(h->off_lab + (resident ? (int)lab.size() * 4 : 0));
     h->off_q = align16(h->off_tab + (int)res.size());
     h->off_m = h->off_q + (kDfaThreads / 64) * kDfaQueue * 16;
-    h->lds_bytes = h->off_m + kDfaMatchCap * 12;
+    h->off_list = h->off_m + kDfaMatchCap * 12;
+    h->lds_bytes = h->off_list + kDfaThreads * 16 * 2;
     if (h->lds_bytes > kDfaLdsLimit) return fail(PFSM_EINVAL, "DFA scan LDS layout does not fit");
 
     int rc;
@@ -393,6 +396,7 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
     a.off_tab = h->off_tab;
     a.off_q = h->off_q;
     a.off_m = h->off_m;
+    a.off_list = h->off_list;
     a.lds_bytes = h->lds_bytes;
     void *args[] = {&a};
     HIP_TRY(hipLaunchCooperativeKernel(h->kernel, dim3(h->n_blocks), dim3(kDfaThreads), args, h->lds_bytes, s));
