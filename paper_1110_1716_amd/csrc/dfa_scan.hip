@@ -5,17 +5,21 @@
 // compute unit when the table is resident in LDS).  Workgroup b owns the
 // start positions of one contiguous segment per round (lazy data
 // partitioning, Section III.D.2: a segment owns its starts, its walks read
-// past its end until they die).  The segment is processed in windows of 16 bytes per thread:
-//   1. the window (12 KiB) is staged from HBM into LDS with 16-byte loads issued two
-//      windows ahead;
-//   2. every start takes its first symbol through the row of q0 cached in LDS
-//      by byte (Section III.B steps 1-4 for the fresh tag), 16 independent
-//      lookups per thread; the live ones take their second symbol through
-//      the table (resident in LDS, or the LDS copies of q0's successor rows);
-//   3. walks still live go to a wave-private LDS queue (ballot + prefix
-//      popcount) and advance in rounds of up to 16 symbols per walk, the
-//      symbols coming from one 16-byte chunk (LDS inside the window, L2
-//      outside it); walks left at the end of a window carry over;
+// past its end until they die), and each wave owns a contiguous slice of the
+// segment, which it works through in 1 KiB windows (16 bytes per lane) with
+// no synchronisation between waves:
+//   1. the wave keeps its window and the next one staged in a private 2 KiB
+//      LDS ring, loading the window after next from HBM while it works;
+//   2. every start takes its first symbol through a byte-indexed liveness
+//      table of q0's row (Section III.B steps 1-4 for the fresh tag), 16
+//      independent lookups per lane; the starts that survive are compacted
+//      (ballot prefix) into a list and take their second symbol through the
+//      table (resident in LDS, or the LDS copies of q0's successor rows)
+//      with every lane busy;
+//   3. walks still live go to a wave-private LDS queue and advance in rounds
+//      of up to 16 symbols while their bytes are staged; a walk that reaches
+//      the end of the staged pair waits for the next window, and the ones
+//      alive at the end of the slice finish reading through L2;
 //   4. every final state entered adds (start, end, label) to an LDS buffer
 //      under the key (start - segment start, k), k = the instance's match
 //      count so far, which orders (end, label) within a start (Section III.B
@@ -31,7 +35,8 @@ namespace pfsmk {
 namespace {
 
 constexpr int NT = kDfaThreads;
-constexpr int W = kDfaWindow;
+constexpr int WIN = kDfaWin;
+constexpr int RING = kDfaRing;
 constexpr int QW = kDfaQueue;
 constexpr int QK = QW / 64;
 constexpr int MC = kDfaMatchCap;
@@ -44,7 +49,7 @@ template <int ENC, bool kId>
 struct DfaCtx {
     const DfaArgs &a;
     const uint8_t *xs;
-    const int32_t *first_s;
+    const uint16_t *f16_s;
     const int16_t *slot_s;
     const int16_t *b2s_s;
     const uint8_t *flags_s;
@@ -56,10 +61,12 @@ struct DfaCtx {
     int32_t *mlab;
     int *mn;
     int *ovf;
-    int64_t wbase;
-    int staged;
-    int64_t seg_lo;
-    int32_t n32;
+    int64_t sl = 0;       // first byte of the wave's slice (ring offsets are relative to it)
+    int32_t sl32 = 0;
+    int64_t wbase = 0;    // current window
+    int staged = 0;       // bytes staged from wbase (at most RING)
+    int64_t seg_lo = 0;
+    int32_t n32 = 0;
     long long T = 0, X = 0, L = 0, M = 0;
 
     static constexpr bool kResident = ENC == kEnc8 || ENC == kEnc8D || ENC == kEnc16;
@@ -69,22 +76,47 @@ struct DfaCtx {
         else return a.flags[s];
     }
     __device__ __forceinline__ int sym(int byte) const { return kId ? byte : (int)b2s_s[byte]; }
+    // Live target of q0 on byte b, or -1.  States below 2^15 come from the
+    // 16-bit row in LDS, larger ones from the row in memory.
+    __device__ __forceinline__ int first_state(int b) const {
+        if constexpr (ENC == kCold32) {
+            return a.first[b];
+        } else {
+            const unsigned v = f16_s[b];
+            return (v & 0x8000u) ? (int)(v & 0x7fffu) : -1;
+        }
+    }
     // delta(s, sy) as given: a state or -1.
     __device__ __forceinline__ int tab(int s, int sy) const {
-        const int64_t i = (int64_t)s * a.n_symbols + sy;
         if constexpr (ENC == kEnc8) {
-            const int v = tab_s[i];
+            const int v = tab_s[(uint32_t)s * (uint32_t)a.n_symbols + (uint32_t)sy];
             return v == 255 ? -1 : v;
         } else if constexpr (ENC == kEnc8D) {
-            const int ns = a.n_states * a.n_symbols;
-            const uint32_t *dead = reinterpret_cast<const uint32_t *>(tab_s + ((ns + 3) & ~3));
-            return (dead[i >> 5] >> (i & 31)) & 1u ? -1 : (int)tab_s[i];
+            // 256 states: the byte and its dead bit are read side by side.
+            const uint32_t i = ((uint32_t)s << 8) | (uint32_t)sy;
+            const uint32_t *dead = reinterpret_cast<const uint32_t *>(tab_s + 65536);
+            const int v = tab_s[i];
+            const uint32_t w = dead[i >> 5];
+            return (w >> (i & 31)) & 1u ? -1 : v;
         } else if constexpr (ENC == kEnc16) {
-            return reinterpret_cast<const int16_t *>(tab_s)[i];
+            return reinterpret_cast<const int16_t *>(tab_s)[(uint32_t)s * (uint32_t)a.n_symbols + (uint32_t)sy];
         } else if constexpr (ENC == kCold16) {
-            return reinterpret_cast<const int16_t *>(a.tbl)[i];
+            return reinterpret_cast<const int16_t *>(a.tbl)[(int64_t)s * a.n_symbols + sy];
         } else {
-            return reinterpret_cast<const int32_t *>(a.tbl)[i];
+            return reinterpret_cast<const int32_t *>(a.tbl)[(int64_t)s * a.n_symbols + sy];
+        }
+    }
+    // delta(s, sy) read without branches (s and sy in range): the reads of a
+    // step can then be issued together.
+    __device__ __forceinline__ int tab_any(int s, int sy) const {
+        if constexpr (ENC == kEnc8D) {
+            const uint32_t i = ((uint32_t)s << 8) | (uint32_t)sy;
+            const uint32_t *dead = reinterpret_cast<const uint32_t *>(tab_s + 65536);
+            const int v = tab_s[i];
+            const uint32_t w = dead[i >> 5];
+            return ((w >> (i & 31)) & 1u) ? -1 : v;
+        } else {
+            return tab(s, sy);
         }
     }
     // Second symbol of a walk whose first step read byte b0 and reached s1.
@@ -127,10 +159,17 @@ struct DfaCtx {
         k += cnt;
     }
     __device__ __forceinline__ int n_labels(int s) const { return lab_lo(s + 1) - lab_lo(s); }
+    // The ring byte of position p (meaningful when p is staged; any p reads
+    // inside the ring).
+    __device__ __forceinline__ int ring_at(int32_t p) const { return xs[(uint32_t)(p - sl32) & (RING - 1)]; }
+    // Whether the 16-byte chunk at p (a multiple of 16) is staged in LDS.
+    __device__ __forceinline__ bool staged_at(int64_t p) const {
+        const int64_t r = p - wbase;
+        return r >= 0 && r + 16 <= staged;
+    }
     // The 16-byte chunk holding position p (p is a multiple of 16).
     __device__ __forceinline__ uint4 chunk(int64_t p) {
-        const int64_t r = p - wbase;
-        if (r >= 0 && r + 16 <= staged) return *reinterpret_cast<const uint4 *>(xs + r);
+        if (staged_at(p)) return *reinterpret_cast<const uint4 *>(xs + ((p - sl) & (RING - 1)));
         ++L;
         return load_granule(a.x, p);
     }
@@ -138,9 +177,16 @@ struct DfaCtx {
 
 // One round: every walk in this wave's queue advances through the rest of
 // the 16-byte chunk holding its next position (up to 16 symbols); walks that
-// end are dropped and the queue is re-packed.
-template <int ENC, bool kId>
-__device__ __forceinline__ void drain_round(DfaCtx<ENC, kId> &c, QEnt *q, int &qcount) {
+// end are dropped and the queue is re-packed.  With kStagedOnly a walk whose
+// chunk is not staged in LDS stays where it is.  Returns whether some kept
+// walk can advance inside the staged window.
+//
+// A step issues the reads of both walks of a lane (the flag of the state just
+// entered and the table entry of the next symbol) before it uses any of
+// them, so the step costs one LDS round trip; reports go through a branch
+// that is taken only when some walk of the wave enters a final state.
+template <bool kStagedOnly, int ENC, bool kId>
+__device__ __forceinline__ bool drain_round(DfaCtx<ENC, kId> &c, QEnt *q, int &qcount) {
     const int lane = lane_id();
     QEnt e[QK];
     bool alive[QK];
@@ -156,59 +202,109 @@ __device__ __forceinline__ void drain_round(DfaCtx<ENC, kId> &c, QEnt *q, int &q
 #pragma unroll
     for (int j = 0; j < QK; ++j) {
         const int64_t c0 = (int64_t)(e[j].pos & ~15);
-        ch[j] = alive[j] ? c.chunk(c0) : make_uint4(0, 0, 0, 0);
+        const bool go = alive[j] && (!kStagedOnly || c.staged_at(c0));
+        ch[j] = go ? c.chunk(c0) : make_uint4(0, 0, 0, 0);
         const int64_t end = c0 + 16 < c.a.n ? c0 + 16 : c.a.n;
-        steps[j] = (int)(end - e[j].pos);  // symbols left in this chunk
+        steps[j] = go ? (int)(end - e[j].pos) : 0;  // symbols left in this chunk
     }
-    // t[j]: target of the walk's next symbol, looked up one step ahead so
-    // that the flag read of a state overlaps the table read of its successor.
+    // t[j]: target of the walk's next symbol (-1: none), looked up a step ahead.
     int t[QK];
 #pragma unroll
     for (int j = 0; j < QK; ++j) {
         const int sy = c.sym(byte_of(ch[j], e[j].pos & 15));
-        t[j] = (alive[j] && sy >= 0) ? c.tab(e[j].state, sy) : -1;
+        const int v = c.tab_any(e[j].state, sy < 0 ? 0 : sy);
+        t[j] = (steps[j] > 0 && sy >= 0) ? v : -1;
     }
 #pragma unroll 1
     for (int st = 0; st < 16; ++st) {
-        bool more = false;
+        uint8_t f[QK];
+        int nx[QK];
 #pragma unroll
         for (int j = 0; j < QK; ++j) {
-            if (alive[j] && st < steps[j]) {
-                ++c.T;
-                const int cur = t[j];
-                if (cur < 0) {
-                    alive[j] = false;
-                } else {
-                    const uint8_t f = c.flag(cur);
-                    int nxt = -1;
-                    if (st + 1 < steps[j]) {
-                        const int sy = c.sym(byte_of(ch[j], (e[j].pos + 1) & 15));
-                        if (sy >= 0) nxt = c.tab(cur, sy);
-                    }
-                    if (!(f & kLive)) {
-                        alive[j] = false;
-                    } else {
-                        ++c.X;
-                        if (f & kFinal) c.emit(e[j].start, e[j].pos, cur, e[j].k);
-                        e[j].state = cur;
-                        ++e[j].pos;
-                        t[j] = nxt;
-                        more |= st + 1 < steps[j];
-                    }
-                }
-            }
+            const int cur = t[j] < 0 ? 0 : t[j];
+            f[j] = c.flag(cur);
+            const int sy = c.sym(byte_of(ch[j], (e[j].pos + 1) & 15));
+            const int v = c.tab_any(cur, sy < 0 ? 0 : sy);
+            nx[j] = (sy >= 0 && st + 1 < steps[j]) ? v : -1;
+        }
+        bool more = false, fin[QK], anyfin = false;
+#pragma unroll
+        for (int j = 0; j < QK; ++j) {
+            const bool act = st < steps[j];
+            const bool ok = act && t[j] >= 0 && (f[j] & kLive);
+            c.T += act ? 1 : 0;
+            c.X += ok ? 1 : 0;
+            fin[j] = ok && (f[j] & kFinal);
+            anyfin |= fin[j];
+            if (act && !ok) steps[j] = 0;  // the walk ends here
+            alive[j] = alive[j] && (!act || ok);
+            e[j].state = ok ? t[j] : e[j].state;
+            e[j].pos += ok ? 1 : 0;
+            t[j] = nx[j];
+            more |= ok && st + 1 < steps[j];
+        }
+        if (__any(anyfin)) {
+#pragma unroll
+            for (int j = 0; j < QK; ++j)
+                if (fin[j]) c.emit(e[j].start, e[j].pos - 1, e[j].state, e[j].k);
         }
         if (!__any(more)) break;
     }
     int nc = 0;
+    bool again = false;
 #pragma unroll
     for (int j = 0; j < QK; ++j) {
         const bool keep = alive[j] && e[j].pos < c.n32;
+        again |= keep && c.staged_at((int64_t)(e[j].pos & ~15));
         const int slot = wave_push_slot(nc, keep);
         if (keep) q[slot] = e[j];
     }
     __builtin_amdgcn_wave_barrier();
     qcount = nc;
+    return __any(again);
+}
+
+// Advances the lane's walk (state s, next position pos) while its bytes are
+// staged: it enters states until one is not live or a byte has no
+// transition, the input ends, or the staged pair ends at `lim`.  Returns
+// whether the walk is still live at `lim` (it then continues in the next
+// window).  One LDS round trip per symbol: the flag of the state just
+// entered, the table entry of the byte after it and the byte after that are
+// read together, before any of them is used.
+template <int ENC, bool kId>
+__device__ __forceinline__ bool advance_staged(DfaCtx<ENC, kId> &c, bool act, int32_t start, int &s, int32_t &pos,
+                                               int32_t &k, int32_t lim) {
+    bool run = act && pos < lim;
+    bool alive = act;
+    int b0 = c.ring_at(pos);
+    int bn = c.ring_at(pos + 1);
+    int sy = c.sym(b0);
+    int t = c.tab_any(s, sy < 0 ? 0 : sy);
+    if (sy < 0) t = -1;
+    int nT = 0, nX = 0;
+    while (__any(run)) {
+        const int cur = t < 0 ? 0 : t;
+        const uint8_t f = c.flag(cur);
+        const int sy2 = c.sym(bn);
+        const int tn = c.tab_any(cur, sy2 < 0 ? 0 : sy2);
+        const int bnn = c.ring_at(pos + 2);
+        const bool ok = run && t >= 0 && (f & kLive);
+        nT += run ? 1 : 0;
+        nX += ok ? 1 : 0;
+        const bool fin = ok && (f & kFinal);
+        if (__any(fin)) {
+            if (fin) c.emit(start, pos, cur, k);
+        }
+        if (run && !ok) alive = false;
+        s = ok ? cur : s;
+        pos += ok ? 1 : 0;
+        run = ok && pos < lim;
+        t = sy2 < 0 ? -1 : tn;
+        bn = bnn;
+    }
+    c.T += nT;
+    c.X += nX;
+    return alive && pos < c.n32;
 }
 
 // The full walk of one start reading the input through the cache hierarchy;
@@ -217,7 +313,7 @@ template <int ENC, bool kId>
 __device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32_t i, bool write, long long at) {
     const DfaArgs &a = c.a;
     long long cnt = 0;
-    int s = c.first_s[a.x[i]];
+    int s = c.first_state(a.x[i]);
     int32_t pos = i;
     while (s >= 0) {
         for (int l = c.lab_lo(s); l < c.lab_lo(s + 1); ++l, ++cnt) {
@@ -235,83 +331,93 @@ __device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32
     return cnt;
 }
 
+// Exclusive prefix over the wave of a count in [0, 16), and the wave total.
+__device__ __forceinline__ int wave_excl_small(int v, int &total) {
+    const unsigned long long below = lanes_below();
+    int ex = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+        const unsigned long long m = __ballot((v >> bit) & 1);
+        ex += __popcll(m & below) << bit;
+        tot += __popcll(m) << bit;
+    }
+    total = tot;
+    return ex;
+}
+
+// Move the walks of this wave's queue to the workgroup's spill area in
+// memory (stores only).  Returns false when the area is full: the segment is
+// then re-walked at its end and the walks are dropped.
+__device__ __forceinline__ bool spill_walks(QEnt *q, int &qcount, QEnt *area, int *sp_n) {
+    int at = 0;
+    if (lane_id() == 0) at = atomicAdd(sp_n, qcount);
+    at = __shfl(at, 0);
+    const bool fits = at + qcount <= kDfaSpill;
+    if (fits)
+        for (int e = lane_id(); e < qcount; e += 64) area[at + e] = q[e];
+    __builtin_amdgcn_wave_barrier();
+    qcount = 0;
+    return fits;
+}
+
 template <int ENC, bool kId>
 __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
+    // States of the 8-bit encodings travel in the live-start list.
+    constexpr bool kPack = ENC == kEnc8 || ENC == kEnc8D;
     extern __shared__ __align__(16) uint8_t lds[];
-    uint8_t *xs = lds;
-    int32_t *first_s = reinterpret_cast<int32_t *>(lds + W);
-    int16_t *slot_s = reinterpret_cast<int16_t *>(first_s + 256);
+    int16_t *slot_s = reinterpret_cast<int16_t *>(lds + kDfaWaves * RING);
     int16_t *b2s_s = slot_s + 256;
+    uint16_t *f16_s = reinterpret_cast<uint16_t *>(b2s_s + 256);
     uint8_t *flags_s = lds + a.off_flags;
     int32_t *laboff_s = reinterpret_cast<int32_t *>(lds + a.off_laboff);
     int32_t *lab_s = reinterpret_cast<int32_t *>(lds + a.off_lab);
     uint8_t *tab_s = lds + a.off_tab;
     QEnt *qall = reinterpret_cast<QEnt *>(lds + a.off_q);
     uint32_t *mkey = reinterpret_cast<uint32_t *>(lds + a.off_m);
-    uint16_t *list_all = reinterpret_cast<uint16_t *>(lds + a.off_list);
     int32_t *mend = reinterpret_cast<int32_t *>(mkey + MC);
     int32_t *mlab = mend + MC;
-    __shared__ int mn, ovf;
+    __shared__ int mn, ovf, sp_n, seg_s, last_s;
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
+    __shared__ long long ex_s;
     __shared__ unsigned epoch_s;
 
     const int tid = threadIdx.x;
     const int wv = tid >> 6;
+    const int lane = lane_id();
     const int b = blockIdx.x;
     const int32_t n32 = (int32_t)a.n;
+    uint8_t *ring = lds + wv * RING;
+    uint32_t *lst = reinterpret_cast<uint32_t *>(lds + a.off_list) + wv * kDfaList;
+    QEnt *spill = reinterpret_cast<QEnt *>(a.spill) + (int64_t)b * kDfaSpill;
 
-    // Issue the first two windows' loads before anything else.
-    auto seg_of = [&](int r, int64_t &lo, int64_t &hi) __attribute__((always_inline)) {
-        lo = ((int64_t)r * a.n_blocks + b) * a.seg;
-        hi = lo + a.seg < a.n ? lo + a.seg : a.n;
-    };
-    int64_t seg_lo, seg_hi;
-    seg_of(0, seg_lo, seg_hi);
-    // Window stream over the rounds: (round, window base) in order.
-    int pr = 0;
-    int64_t pw = seg_lo, plo = seg_lo, phi = seg_hi;
-    auto next_window = [&](int64_t &wb, bool &ok) __attribute__((always_inline)) {
-        // advance (pr, pw) to the next window that has starts
-        while (pr < a.n_rounds) {
-            if (pw < phi) {
-                wb = pw;
-                pw += W;
-                ok = true;
-                return;
-            }
-            ++pr;
-            if (pr < a.n_rounds) {
-                seg_of(pr, plo, phi);
-                pw = plo;
-            }
-        }
-        ok = false;
-    };
-    auto fetch = [&](int64_t wb, uint4 &v) __attribute__((always_inline)) {
-        const int64_t p = wb + 16 * tid;
-        v = p < a.n ? load_granule(a.x, p) : make_uint4(0, 0, 0, 0);
-    };
-    // Two prefetch buffers used alternately: buffer p holds the window
-    // after next while the other one's window is being processed.
-    int64_t pwb[2] = {0, 0};
-    bool pok[2] = {false, false};
-    uint4 pv[2];
-    next_window(pwb[0], pok[0]);
-    if (pok[0]) fetch(pwb[0], pv[0]);
-    next_window(pwb[1], pok[1]);
-    if (pok[1]) fetch(pwb[1], pv[1]);
-
-    // Tables into LDS.
+    if (tid == 0) {
+        seg_s = take_ticket(a.ctl);
+        epoch_s = lb_epoch(a.ctl);
+        mn = 0;
+        ovf = 0;
+        sp_n = 0;
+    }
+    // Tables into LDS: every load of a thread is issued before its stores.
     if (tid < 256) {
-        first_s[tid] = a.first[tid];
+        const int f = a.first[tid];
+        f16_s[tid] = f >= 0 ? (uint16_t)(0x8000u | ((unsigned)f & 0x7fffu)) : (uint16_t)0;
         slot_s[tid] = a.first_slot[tid];
         b2s_s[tid] = a.b2s[tid];
     }
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.res);
         uint4 *dst = reinterpret_cast<uint4 *>(tab_s);
-        for (int i = tid; i < (a.res_bytes >> 4); i += NT) dst[i] = src[i];
+        const int n16 = a.res_bytes >> 4;
+        int i = tid;
+        for (; i + 3 * NT < n16; i += 4 * NT) {
+            const uint4 v0 = src[i], v1 = src[i + NT], v2 = src[i + 2 * NT], v3 = src[i + 3 * NT];
+            dst[i] = v0;
+            dst[i + NT] = v1;
+            dst[i + 2 * NT] = v2;
+            dst[i + 3 * NT] = v3;
+        }
+        for (; i < n16; i += NT) dst[i] = src[i];
     }
     if (DfaCtx<ENC, kId>::kResident) {
         for (int i = tid; i < a.n_states; i += NT) flags_s[i] = a.flags[i];
@@ -319,113 +425,144 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         const int nnz = a.lab_off[a.n_states];
         for (int i = tid; i < nnz; i += NT) lab_s[i] = a.lab[i];
     }
-    if (tid == 0) {
-        mn = 0;
-        ovf = 0;
-        epoch_s = first_epoch(a.slots, b);
-    }
     __syncthreads();
-    const unsigned epoch0 = epoch_s;
+    const unsigned epoch = epoch_s;
 
-    DfaCtx<ENC, kId> c{a, xs, first_s, slot_s, b2s_s, flags_s, laboff_s, lab_s, tab_s, mkey,
-                       mend, mlab, &mn, &ovf, 0, 0, 0, n32};
+    DfaCtx<ENC, kId> c{a, ring, f16_s, slot_s, b2s_s, flags_s, laboff_s, lab_s, tab_s, mkey, mend, mlab, &mn, &ovf};
+    c.n32 = n32;
     QEnt *q = qall + wv * QW;
     int qcount = 0;
-    long long base_out = 0;
 
-    // Process the window held in prefetch buffer p, then refill p with the
-    // window two ahead.  Called with p = 0, 1, 0, 1, ... (static indices).
-    auto run_window = [&](const int p) __attribute__((always_inline)) {
-        const int64_t wbase = pwb[p];
-        const int64_t wend = wbase + W < seg_hi ? wbase + W : seg_hi;
-        const int64_t rest = a.n - wbase;
-        const int staged = (int)(rest < W ? rest : W);
-        __syncthreads();  // every wave is done with the previous window's bytes
-        *reinterpret_cast<uint4 *>(xs + 16 * tid) = pv[p];
-        const uint4 mine = pv[p];
-        next_window(pwb[p], pok[p]);
-        if (pok[p]) fetch(pwb[p], pv[p]);
-        __syncthreads();
-        c.wbase = wbase;
-        c.staged = staged;
-
-        // Symbol one for the 16 starts owned by this thread: 16 independent
-        // lookups of the q0 row, giving the mask of live instances.
-        const int il0 = 16 * tid;
-        const int64_t i0 = wbase + il0;
-        const int64_t nv64 = wend - i0;
-        const int nvalid = nv64 <= 0 ? 0 : (nv64 >= 16 ? 16 : (int)nv64);
-        unsigned lm = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-            if (k < nvalid && first_s[byte_of(mine, k)] >= 0) lm |= 1u << k;
-        c.T += nvalid;
-        c.X += __popc(lm);
-        // Compact the wave's live instances into its LDS list (prefix sum of
-        // the lanes' counts), then advance them with every lane busy.
-        const int cnt = __popc(lm);
-        const int incl = (int)wave_incl_scan(cnt);
-        const int total = __shfl(incl, 63);
-        int off = incl - cnt;
-        uint16_t *lst = list_all + wv * (64 * 16);
-        while (lm) {
-            const int k = __ffs(lm) - 1;
-            lm &= lm - 1;
-            lst[off++] = (uint16_t)(il0 + k);
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int e0 = 0; e0 < total; e0 += 64) {
-            const int e = e0 + lane_id();
-            bool push = false;
-            QEnt ent{0, 0, 0, 0};
-            if (e < total) {
-                const int il = lst[e];
-                const int32_t i = (int32_t)(wbase + il);
-                const int b0 = xs[il];
-                const int s1 = first_s[b0];
-                int32_t km = 0;
-                if (c.flag(s1) & kFinal) c.emit(i, i, s1, km);
-                if (i + 1 < n32) {
-                    ++c.T;
-                    const int b1 = il + 1 < staged ? xs[il + 1] : a.x[i + 1];
-                    const int sy = c.sym(b1);
-                    const int t2 = sy < 0 ? -1 : c.live(c.tab2(b0, s1, sy));
-                    if (t2 >= 0) {
-                        ++c.X;
-                        if (c.flag(t2) & kFinal) c.emit(i, i + 1, t2, km);
-                        if (i + 2 < n32) {
-                            push = true;
-                            ent = QEnt{i, t2, i + 2, km};
-                        }
-                    }
-                }
-            }
-            while (qcount > QW - 64) drain_round(c, q, qcount);
-            const int slot = wave_push_slot(qcount, push);
-            if (push) q[slot] = ent;
-        }
+    auto fetch = [&](int64_t wb) __attribute__((always_inline)) {
+        const int64_t p = wb + 16 * lane;
+        return p < a.n ? load_granule(a.x, p) : make_uint4(0, 0, 0, 0);
     };
 
-    for (int r = 0; r < a.n_rounds; ++r) {
-        seg_of(r, seg_lo, seg_hi);
+    for (;;) {
+        const int sg = seg_s;
+        if (sg >= a.n_segs) break;
+        const int64_t seg_lo = (int64_t)sg * a.seg;
+        const int64_t seg_hi = seg_lo + a.seg < a.n ? seg_lo + a.seg : a.n;
+        // The wave's slice of the segment: a multiple of 16 bytes per wave.
+        const int64_t per = ((seg_hi - seg_lo + 16 * kDfaWaves - 1) / (16 * kDfaWaves)) * 16;
+        int64_t sl = seg_lo + per * wv;
+        const int64_t sh = sl + per < seg_hi ? sl + per : seg_hi;
+        if (sl > seg_hi) sl = seg_hi;
+        uint4 cur = sl < sh ? fetch(sl) : make_uint4(0, 0, 0, 0);
+        uint4 nxt = sl < sh && sl + WIN < a.n ? fetch(sl + WIN) : make_uint4(0, 0, 0, 0);
         c.seg_lo = seg_lo;
+        c.sl = sl;
+        c.sl32 = (int32_t)sl;
         const long long m_before = c.M;
-        auto in_round = [&](int p) __attribute__((always_inline)) { return pok[p] && pwb[p] >= seg_lo && pwb[p] < seg_hi; };
-        for (;;) {
-            if (!in_round(0)) break;
-            run_window(0);
-            if (!in_round(1)) break;
-            run_window(1);
-        }
-        // The round's walks run to their end.
-        while (qcount > 0) drain_round(c, q, qcount);
+        if (sl < sh) *reinterpret_cast<uint4 *>(ring + 16 * lane) = cur;
 
-        // Offsets: this round's count, the peers' counts, placement.
+        for (int64_t wb = sl; wb < sh; wb += WIN) {
+            // Stage the next window beside this one and request the one after.
+            const int rb = (int)((wb - sl) & (RING - 1));
+            *reinterpret_cast<uint4 *>(ring + ((rb + WIN) & (RING - 1)) + 16 * lane) = nxt;
+            const uint4 after = nxt;
+            if (wb + WIN < sh && wb + 2 * WIN < a.n) nxt = fetch(wb + 2 * WIN);
+            __builtin_amdgcn_wave_barrier();
+            c.wbase = wb;
+            const int64_t rest = a.n - wb;
+            c.staged = (int)(rest < RING ? rest : RING);
+
+            // The staged pair ends at lim.
+            const int32_t lim = (int32_t)(rest < RING ? a.n : wb + RING);
+
+            // Walks parked at the end of the previous window continue.
+            {
+                const int n_old = qcount;
+                qcount = 0;
+                for (int e0 = 0; e0 < n_old; e0 += 64) {
+                    const int e = e0 + lane;
+                    const bool act = e < n_old;
+                    QEnt w = act ? q[e] : QEnt{0, 0, 0, 0};
+                    __builtin_amdgcn_wave_barrier();
+                    const bool park = advance_staged(c, act, w.start, w.state, w.pos, w.k, lim);
+                    const int slot = wave_push_slot(qcount, park);
+                    if (park) q[slot] = w;
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+
+            // Starts owned in this window: [wb, min(wb + WIN, sh)).
+            const int64_t own_end = wb + WIN < sh ? wb + WIN : sh;
+            const int64_t nv64 = own_end - (wb + 16 * lane);
+            const int nvalid = nv64 <= 0 ? 0 : (nv64 >= 16 ? 16 : (int)nv64);
+            const unsigned vmask = nvalid >= 16 ? 0xffffu : ((1u << nvalid) - 1u);
+            c.T += nvalid;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                // Symbol one for 8 starts per lane (q0's row by byte), then the
+                // list of survivors: offset | state << 10 when states fit 8
+                // bits, else the offset alone.
+                unsigned lm = 0;
+                uint32_t ent8[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const unsigned v = f16_s[byte_of(cur, 8 * h + k)];
+                    lm |= (v >> 15) << k;
+                    ent8[k] = kPack ? ((uint32_t)(16 * lane + 8 * h + k) | ((v & 0xffu) << 10))
+                                    : (uint32_t)(16 * lane + 8 * h + k);
+                }
+                lm &= (vmask >> (8 * h)) & 0xffu;
+                const int cnt = __popc(lm);
+                c.X += cnt;
+                int total;
+                const int ex = wave_excl_small(cnt, total);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if ((lm >> k) & 1u) lst[ex + __popc(lm & ((1u << k) - 1u))] = ent8[k];
+                __builtin_amdgcn_wave_barrier();
+                for (int e0 = 0; e0 < total; e0 += 64) {
+                    const int e = e0 + lane;
+                    const bool act = e < total;
+                    const uint32_t w = act ? lst[e] : 0u;
+                    const int il = (int)(w & 1023u);
+                    const int32_t i = (int32_t)(wb + il);
+                    int s1 = kPack ? (int)(w >> 10) : c.first_state(c.ring_at(i));
+                    if (!act) s1 = 0;
+                    int32_t km = 0;
+                    if (act && (c.flag(s1) & kFinal)) c.emit(i, i, s1, km);
+                    int32_t pos = i + 1;
+                    const bool park = advance_staged(c, act && pos < n32, i, s1, pos, km, lim);
+                    if (qcount > QW - 64 && __any(park)) {
+                        // Too many walks wait for the next window: move them
+                        // to memory (they finish at the end of the slice).
+                        if (!spill_walks(q, qcount, spill, &sp_n)) ovf = 1;
+                    }
+                    const int slot = wave_push_slot(qcount, park);
+                    if (park) q[slot] = QEnt{i, s1, pos, km};
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            cur = after;
+        }
+        // The slice's walks run to their end, then the parked ones.
+        while (qcount > 0) drain_round<false>(c, q, qcount);
+        __syncthreads();
+        const int n_sp = ovf ? 0 : sp_n;
+        for (int e0 = 64 * wv; e0 < n_sp; e0 += NT) {
+            const int e = e0 + lane;
+            if (e < n_sp) q[lane] = spill[e];
+            qcount = n_sp - e0 < 64 ? n_sp - e0 : 64;
+            __builtin_amdgcn_wave_barrier();
+            while (qcount > 0) drain_round<false>(c, q, qcount);
+        }
+
+        // The segment's count, its offset by look-back, and placement.
         const long long mine_m = block_sum<NT>(c.M - m_before, red);
-        long long round_total;
-        const long long excl =
-            grid_prefix<NT>(a.slots, a.n_blocks, b, (epoch0 + r) & kEpochMask, mine_m, red, &round_total);
-        const long long at0 = base_out + excl;
+        if (tid == 0) seg_s = take_ticket(a.ctl);  // the next segment, requested early
+        if (wv == 0) {
+            const long long ex = lookback(a.lb, sg, epoch, mine_m);
+            if (lane == 0) {
+                ex_s = ex;
+                if (sg == a.n_segs - 1) *a.total = ex + mine_m;
+            }
+        }
+        __syncthreads();
+        const long long at0 = ex_s;
         if (!ovf) {
             // Rank of every buffered match in (start, end, label) order:
             // bucket by start offset / 64 (histogram, scan, scatter), then
@@ -491,20 +628,21 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
                 run += ctot;
             }
         }
-        base_out += round_total;
         __syncthreads();
         if (tid == 0) {
             mn = 0;
             ovf = 0;
+            sp_n = 0;
         }
+        __syncthreads();
     }
-    if (b == 0 && tid == 0) *a.total = base_out;
     long long st4[4] = {c.T, c.X, c.L, c.M};
     block_sum4<NT>(st4, red4);
     if (tid == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) a.bstats[4 * b + k] = st4[k];
     }
+    finish_launch<NT>(a.ctl, a.lb, a.lb_cap, &last_s);
 }
 
 __global__ void write_zero_kernel(int64_t *p) { *p = 0; }

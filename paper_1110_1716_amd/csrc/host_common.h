@@ -71,13 +71,23 @@ struct DevBuf {
     }
 };
 
+// Segments a launch may have: inputs are below 2^31 bytes and a segment
+// holds at least min(n / grid, 64 KiB) bytes.
+constexpr int kMaxSegs = 32768;
+
 // Scan scratch of one handle on one stream: the persistent grid's count
-// slots (zeroed once, epoch-tagged afterwards), per-workgroup work counters,
-// the device total and pinned host mirrors for reading them back.
+// slots (zeroed once, epoch-tagged afterwards), the segment tickets and
+// look-back words, per-workgroup work counters, the device total and pinned
+// host mirrors for reading them back.
 struct Workspace {
     hipStream_t stream = nullptr;
     int n_blocks = 0;
+    int last_grid = 0;                    // workgroups of the last launch
     unsigned long long *slots = nullptr;  // [n_blocks]
+    ScanCtl *ctl = nullptr;
+    unsigned long long *lb = nullptr;     // [lb_cap]
+    int lb_cap = 0;
+    void *spill = nullptr;                // DFA: [n_blocks * kDfaSpill] walks
     long long *bstats = nullptr;          // [n_blocks * 4]
     int64_t *d_total = nullptr;
     int64_t *h_total = nullptr;           // pinned
@@ -91,6 +101,9 @@ struct Workspace {
 
     ~Workspace() {
         if (slots) (void)hipFree(slots);
+        if (ctl) (void)hipFree(ctl);
+        if (lb) (void)hipFree(lb);
+        if (spill) (void)hipFree(spill);
         if (bstats) (void)hipFree(bstats);
         if (d_total) (void)hipFree(d_total);
         if (h_total) (void)hipHostFree(h_total);
@@ -118,6 +131,11 @@ struct WorkspacePool {
         w->n_blocks = n_blocks;
         HIP_TRY(hipMalloc(&w->slots, sizeof(unsigned long long) * n_blocks));
         HIP_TRY(hipMemset(w->slots, 0, sizeof(unsigned long long) * n_blocks));
+        HIP_TRY(hipMalloc(&w->ctl, sizeof(ScanCtl)));
+        HIP_TRY(hipMemset(w->ctl, 0, sizeof(ScanCtl)));
+        w->lb_cap = kMaxSegs + n_blocks;
+        HIP_TRY(hipMalloc(&w->lb, sizeof(unsigned long long) * w->lb_cap));
+        HIP_TRY(hipMemset(w->lb, 0, sizeof(unsigned long long) * w->lb_cap));
         HIP_TRY(hipMalloc(&w->bstats, sizeof(long long) * 4 * n_blocks));
         HIP_TRY(hipMemset(w->bstats, 0, sizeof(long long) * 4 * n_blocks));
         HIP_TRY(hipMalloc(&w->d_total, sizeof(int64_t)));
@@ -158,11 +176,12 @@ inline int align_input(Workspace *w, const uint8_t **x, int64_t n, hipStream_t s
 
 // Sum the per-workgroup counters of the last scan in `w` (synchronises).
 inline int workspace_stats(Workspace *w, long long v[4]) {
-    HIP_TRY(hipMemcpyAsync(w->h_stats, w->bstats, sizeof(long long) * 4 * w->n_blocks, hipMemcpyDeviceToHost,
-                           w->stream));
-    HIP_TRY(hipStreamSynchronize(w->stream));
+    const int g = w->last_grid;
     for (int k = 0; k < 4; ++k) v[k] = 0;
-    for (int b = 0; b < w->n_blocks; ++b)
+    if (g <= 0) return PFSM_OK;
+    HIP_TRY(hipMemcpyAsync(w->h_stats, w->bstats, sizeof(long long) * 4 * g, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    for (int b = 0; b < g; ++b)
         for (int k = 0; k < 4; ++k) v[k] += w->h_stats[4 * b + k];
     return PFSM_OK;
 }

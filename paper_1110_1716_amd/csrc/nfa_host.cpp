@@ -473,6 +473,7 @@ int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64
     a.big_bits = w->big_bits;
     void *args[] = {&a};
     HIP_TRY(hipLaunchCooperativeKernel(nfa_kernel_fn(), dim3(h->n_blocks), dim3(kNfaThreads), args, 0, s));
+    w->last_grid = h->n_blocks;
     w->scanned = true;
     return PFSM_OK;
 }

@@ -11,13 +11,32 @@ namespace pfsmk {
 constexpr uint8_t kLive = 1;   // some final state with an enabled label is reachable
 constexpr uint8_t kFinal = 2;  // the state carries at least one enabled label
 
-// Cross-workgroup count slot: a 24-bit epoch over a 40-bit count.  Every
-// workgroup of the persistent grid rewrites its slot once per round, so all
-// slots always carry the same epoch when a launch begins; a workgroup reads
-// its own slot's epoch, adds one, and waits for its peers to reach it.
+// Cross-workgroup count slot of the NFA's persistent grid: a 24-bit epoch
+// over a 40-bit count.  Every workgroup rewrites its slot once per round, so
+// all slots carry the same epoch when a launch begins; a workgroup reads its
+// own slot's epoch, adds one, and waits for its peers to reach it.
 constexpr int kEpochShift = 40;
 constexpr unsigned long long kCountMask = (1ull << kEpochShift) - 1;
 constexpr unsigned kEpochMask = (1u << 24) - 1;
+
+// Scan control block of a workspace (device memory, zeroed once).  Segments
+// are handed out in order by `ticket`; `done` counts the workgroups that have
+// finished, and the last one resets both and advances `epoch`, so successive
+// launches (or replays of a captured launch) need no host bookkeeping.
+struct ScanCtl {
+    unsigned long long ticket;
+    unsigned epoch;
+    unsigned done;
+};
+
+// Look-back word of a segment: epoch (22 bits) | status (2 bits) | value
+// (40 bits, saturating).  Status 1: the value is the segment's own count;
+// status 2: the value is the count up to and including the segment.
+constexpr int kLbStatShift = 40;
+constexpr int kLbEpochShift = 42;
+constexpr unsigned long long kLbValMask = (1ull << 40) - 1;
+constexpr unsigned kLbEpochMod = (1u << 22) - 1;  // epochs in use: 1 .. kLbEpochMod
+constexpr int kLbAgg = 1, kLbIncl = 2;
 
 struct MatchOut {
     int32_t start, end, label;
@@ -26,11 +45,15 @@ struct MatchOut {
 // ---------------------------------------------------------------- DFA scan
 
 constexpr int kDfaThreads = 768;               // one workgroup, 12 wave64
-constexpr int kDfaWindow = kDfaThreads * 16;   // 16 bytes per thread
+constexpr int kDfaWaves = kDfaThreads / 64;
+constexpr int kDfaWin = 1024;                  // bytes per wave window, 16 per lane
+constexpr int kDfaRing = 2 * kDfaWin;          // staged bytes per wave: window and the next
 constexpr int kDfaSegMax = 65536;              // bytes per workgroup and round
 constexpr int kDfaQueue = 128;                 // LDS queue entries per wave
+constexpr int kDfaList = kDfaWin / 2;          // live-start list per wave (half a window), 32-bit entries
 constexpr int kDfaMatchCap = 1024;             // LDS match buffer per workgroup
-constexpr int kDfaLdsLimit = 160 * 1024;       // LDS per compute unit (gfx950)
+constexpr int kDfaSpill = 4096;                // walks a workgroup can park in memory per segment
+constexpr int kDfaLdsLimit = 159 * 1024;       // dynamic LDS: 160 KiB per CU less the static variables
 constexpr int kDfaTableBudget = 96 * 1024;     // resident table bytes
 constexpr int kDfaHotBudget = 48 * 1024;       // cached rows when not resident
 
@@ -64,17 +87,20 @@ struct DfaArgs {
     MatchOut *out;
     int64_t cap;
     int64_t *total;             // grand total (device)
-    unsigned long long *slots;  // [n_blocks] epoch | count
-    long long *bstats;          // [n_blocks * 4] T, X, long walks, matches
-    int64_t seg;                // bytes per workgroup per round (multiple of 16)
-    int32_t n_blocks;           // persistent grid size
-    int32_t n_rounds;
+    ScanCtl *ctl;
+    unsigned long long *lb;     // [lb_cap] look-back words, one per segment
+    int32_t lb_cap;
+    int32_t n_segs;             // segments of this launch
+    long long *bstats;          // [gridDim.x * 4] T, X, long walks, matches
+    void *spill;                // [gridDim.x * kDfaSpill] walks parked out of LDS
+    int64_t seg;                // bytes per segment (multiple of 16)
     // dynamic LDS layout, byte offsets
     int32_t off_flags, off_laboff, off_lab, off_tab, off_q, off_m, off_list, lds_bytes;
 };
 
-// Fixed part of the DFA kernel's dynamic LDS (window, q0 row, slots, map).
-constexpr int kDfaLdsFixed = kDfaWindow + 256 * 4 + 256 * 2 + 256 * 2;
+// Fixed LDS head: wave rings, hot-row slot by byte, byte map, q0's live
+// target by byte as 16-bit words (bit 15: live, bits 0-14: the state).
+constexpr int kDfaLdsFixed = kDfaWaves * kDfaRing + 256 * 2 + 256 * 2 + 256 * 2;
 
 // Host-side kernel handles (defined in the .hip translation units).
 const void *dfa_kernel_fn(int enc, bool identity_map);

@@ -39,6 +39,8 @@ struct pfsm {
     // ---- DFA: host copy (used to rebuild caches when a label is removed)
     int32_t n_states = 0, n_symbols = 0, q0 = 0;
     bool identity = true;
+    bool dev_identity = true;                  // the device table is indexed by byte
+    int32_t dev_symbols = 0;                   // columns of the device table
     std::vector<int16_t> b2s;                  // [256]
     std::vector<int32_t> delta;                // [n_states * n_symbols]
     std::vector<std::vector<int32_t>> labels;  // per state: sorted unique labels
@@ -137,10 +139,29 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
         off[q + 1] = (int32_t)lab.size();
     }
 
+    // An automaton over a byte map whose byte-indexed 8-bit table fits LDS
+    // is expanded to bytes, so the kernel indexes the table by the byte.
+    const int64_t ns_b = (int64_t)N * 256;
+    const int64_t expanded_bytes = N <= 255 ? ns_b : ns_b + ns_b / 8;
+    const bool expand = !h->identity && N <= 256 && expanded_bytes <= kDfaTableBudget;
+    std::vector<int32_t> dexp;
+    const int32_t *dl = h->delta.data();
+    int32_t SD = S;
+    if (expand) {
+        dexp.resize(ns_b);
+        for (int32_t q = 0; q < N; ++q)
+            for (int b = 0; b < 256; ++b) {
+                const int sy = h->b2s[b];
+                dexp[(int64_t)q * 256 + b] = sy < 0 ? -1 : h->delta[(int64_t)q * S + sy];
+            }
+        dl = dexp.data();
+        SD = 256;
+    }
+
     // Transition table image for LDS.  A resident encoding keeps the whole
     // table, the flags and the label CSR in LDS; when none fits, the table is
     // read through L2 and the rows of q0's live successors are copied.
-    const int64_t ns = (int64_t)N * S;
+    const int64_t ns = (int64_t)N * SD;
     std::vector<uint8_t> res;
     std::vector<int16_t> first_slot(256, -1);
     int n_hot = 0;
@@ -155,28 +176,29 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
         off = align16(off + (tab_bytes + 15) / 16 * 16 + 16);
         off += (kDfaThreads / 64) * kDfaQueue * 16;
         off += kDfaMatchCap * 12;
-        return off + kDfaThreads * 16 * 2;
+        return off + kDfaWaves * kDfaList * 4;
     };
     const int64_t bytes8 = ns, bytes8d = ((ns + 3) & ~3ll) + (ns + 31) / 32 * 4, bytes16 = ns * 2;
     if (N <= 255 && bytes8 <= kDfaTableBudget && lds_total(bytes8, true) <= kDfaLdsLimit) {
         enc = kEnc8;
         res.resize(ns);
-        for (int64_t i = 0; i < ns; ++i) res[i] = h->delta[i] < 0 ? 255 : (uint8_t)h->delta[i];
+        for (int64_t i = 0; i < ns; ++i) res[i] = dl[i] < 0 ? 255 : (uint8_t)dl[i];
     } else if (N == 256 && bytes8d <= kDfaTableBudget && lds_total(bytes8d, true) <= kDfaLdsLimit) {
         enc = kEnc8D;
         const int64_t dead_off = (ns + 3) & ~3ll;
         res.assign(bytes8d, 0);
         uint32_t *dead = reinterpret_cast<uint32_t *>(res.data() + dead_off);
         for (int64_t i = 0; i < ns; ++i) {
-            if (h->delta[i] < 0) dead[i >> 5] |= 1u << (i & 31);
-            else res[i] = (uint8_t)h->delta[i];
+            if (dl[i] < 0) dead[i >> 5] |= 1u << (i & 31);
+            else res[i] = (uint8_t)dl[i];
         }
     } else if (N <= 32767 && bytes16 <= kDfaTableBudget && lds_total(bytes16, true) <= kDfaLdsLimit) {
         enc = kEnc16;
         res.resize(bytes16);
         int16_t *t = reinterpret_cast<int16_t *>(res.data());
-        for (int64_t i = 0; i < ns; ++i) t[i] = (int16_t)h->delta[i];
+        for (int64_t i = 0; i < ns; ++i) t[i] = (int16_t)dl[i];
     } else {
+        SD = S;  // the cold encodings read the table as loaded
         enc = h->tbl16 ? kCold16 : kCold32;
         const int elem = h->tbl16 ? 2 : 4;
         const int max_hot = (int)std::min<int64_t>(32767, kDfaHotBudget / ((int64_t)S * elem));
@@ -216,7 +238,7 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     h->off_q = align16(h->off_tab + (int)res.size());
     h->off_m = h->off_q + (kDfaThreads / 64) * kDfaQueue * 16;
     h->off_list = h->off_m + kDfaMatchCap * 12;
-    h->lds_bytes = h->off_list + kDfaThreads * 16 * 2;
+    h->lds_bytes = h->off_list + kDfaWaves * kDfaList * 4;
     if (h->lds_bytes > kDfaLdsLimit) return fail(PFSM_EINVAL, "DFA scan LDS layout does not fit");
 
     int rc;
@@ -231,7 +253,9 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     h->n_hot = n_hot;
     h->res_bytes = (int32_t)res.size();
 
-    h->kernel = dfa_kernel_fn(enc, h->identity);
+    h->dev_identity = h->identity || (expand && SD == 256);
+    h->dev_symbols = SD;
+    h->kernel = dfa_kernel_fn(enc, h->dev_identity);
     if (!h->kernel) return fail(PFSM_EINVAL, "no DFA kernel for encoding %d", enc);
     HIP_TRY(hipFuncSetAttribute(h->kernel, hipFuncAttributeMaxDynamicSharedMemorySize, h->lds_bytes));
     int occ = 0, cus = 0;
@@ -375,7 +399,7 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
     a.res = h->d_res.p;
     a.res_bytes = h->res_bytes;
     a.n_states = h->n_states;
-    a.n_symbols = h->n_symbols;
+    a.n_symbols = h->dev_symbols;
     a.b2s = h->d_b2s.as<int16_t>();
     a.first = h->d_first.as<int32_t>();
     a.first_slot = h->d_first_slot.as<int16_t>();
@@ -386,10 +410,19 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
     a.out = reinterpret_cast<MatchOut *>(d_out);
     a.cap = cap;
     a.total = d_n_matches;
-    a.slots = w->slots;
+    if (!w->spill) HIP_TRY(hipMalloc(&w->spill, (size_t)h->n_blocks * kDfaSpill * 16));
+    a.ctl = w->ctl;
+    a.lb = w->lb;
+    a.lb_cap = w->lb_cap;
     a.bstats = w->bstats;
-    a.n_blocks = h->n_blocks;
-    plan_segments(n, h->n_blocks, kDfaSegMax, &a.seg, &a.n_rounds);
+    a.spill = w->spill;
+    int rounds;
+    plan_segments(n, h->n_blocks, kDfaSegMax, &a.seg, &rounds);
+    const int64_t n_segs = (n + a.seg - 1) / a.seg;
+    if (n_segs > w->lb_cap) return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)",
+                                        (long long)n, (long long)n_segs, w->lb_cap);
+    a.n_segs = (int32_t)n_segs;
+    const int grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
     a.off_flags = h->off_flags;
     a.off_laboff = h->off_laboff;
     a.off_lab = h->off_lab;
@@ -399,7 +432,8 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
     a.off_list = h->off_list;
     a.lds_bytes = h->lds_bytes;
     void *args[] = {&a};
-    HIP_TRY(hipLaunchCooperativeKernel(h->kernel, dim3(h->n_blocks), dim3(kDfaThreads), args, h->lds_bytes, s));
+    HIP_TRY(hipLaunchKernel(h->kernel, dim3(grid), dim3(kDfaThreads), args, h->lds_bytes, s));
+    w->last_grid = grid;
     w->scanned = true;
     return PFSM_OK;
 }

@@ -139,6 +139,96 @@ __device__ __forceinline__ long long grid_prefix(unsigned long long *slots, int 
     return e;
 }
 
+__device__ __forceinline__ unsigned long long lb_pack(unsigned epoch, int status, long long v) {
+    const unsigned long long u = v < 0 ? 0ull : ((unsigned long long)v > kLbValMask ? kLbValMask : (unsigned long long)v);
+    return ((unsigned long long)epoch << kLbEpochShift) | ((unsigned long long)status << kLbStatShift) | u;
+}
+
+// The epoch of this launch's look-back words (never 0, the value of a
+// cleared word).
+__device__ __forceinline__ unsigned lb_epoch(const ScanCtl *ctl) {
+    const unsigned e = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return e % kLbEpochMod + 1;
+}
+
+// Next segment for this workgroup (thread 0 only).
+__device__ __forceinline__ int take_ticket(ScanCtl *ctl) {
+    return (int)atomicAdd(&ctl->ticket, 1ull);
+}
+
+// Decoupled look-back over segments in ticket order, run by one whole wave
+// once segment s has been scanned: publishes its count, sums the counts of
+// its predecessors back to the nearest one that has published a prefix,
+// publishes its own prefix and returns the sum before s (every lane).  The
+// predecessors of s took their tickets before s did, so their workgroups are
+// running, and each publishes its count before it looks back itself: the
+// waits end whether or not the whole grid is resident.
+__device__ __forceinline__ long long lookback(unsigned long long *lb, int s, unsigned epoch, long long agg) {
+    const int lane = lane_id();
+    if (s == 0) {
+        if (lane == 0) slot_store(&lb[0], lb_pack(epoch, kLbIncl, agg));
+        return 0;
+    }
+    if (lane == 0) slot_store(&lb[s], lb_pack(epoch, kLbAgg, agg));
+    long long ex = 0;
+    int hi = s - 1;
+    for (;;) {
+        const int j = hi - lane;  // lane 0 is the nearest predecessor
+        int st = kLbIncl;
+        long long v = 0;
+        if (j >= 0) {
+            const unsigned long long w = slot_load(&lb[j]);
+            st = (unsigned)(w >> kLbEpochShift) == epoch ? (int)((w >> kLbStatShift) & 3u) : 0;
+            v = (long long)(w & kLbValMask);
+        }
+        const unsigned long long m_inc = __ballot(st == kLbIncl);
+        const unsigned long long m_none = __ballot(st == 0);
+        if (m_inc) {
+            const int k = __ffsll((long long)m_inc) - 1;
+            const unsigned long long need = k == 63 ? ~0ull : ((2ull << k) - 1ull);
+            if ((m_none & need) == 0) {
+                ex += wave_sum(lane <= k ? v : 0);
+                break;
+            }
+        } else if (m_none == 0) {
+            ex += wave_sum(v);
+            hi -= 64;
+            continue;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) slot_store(&lb[s], lb_pack(epoch, kLbIncl, agg + ex));
+    return ex;
+}
+
+// End of a workgroup's part of a launch (call from every thread; contains
+// barriers).  The last workgroup to finish resets the ticket counter and
+// advances the epoch; when the epoch is about to wrap it first clears the
+// look-back words, so a word left from an earlier launch never carries the
+// epoch in use.
+template <int NT>
+__device__ __forceinline__ void finish_launch(ScanCtl *ctl, unsigned long long *lb, int lb_cap, int *flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned d = atomicAdd(&ctl->done, 1u);
+        *flag = d + 1 == gridDim.x;
+    }
+    __syncthreads();
+    if (!*flag) return;
+    __threadfence();
+    const unsigned e = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool wrap = (e + 1) % kLbEpochMod == 0;
+    if (wrap)
+        for (int i = threadIdx.x; i < lb_cap; i += NT) slot_store(&lb[i], 0ull);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&ctl->ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->epoch, wrap ? 0u : e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // The 16-byte granule of a 16-byte aligned input starting at `pos` (a
 // multiple of 16 below n).  Bytes at or past n are unspecified: callers never
 // use them.  The granule holds at least one valid byte, so it lies on a page
