@@ -13,6 +13,7 @@ scan kernel and the CPU oracle's throughput on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +41,34 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ["paper_1110_1716_amd/csrc/dfa_scan.hip", "paper_1110_1716_amd/csrc/scan_common.h",
+                  "paper_1110_1716_amd/csrc/pfsm_dev.h"]
+TRAFFIC_PROFILE = "profiles/dfa_scan_cfg2_hbm_traffic.txt"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the scan kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by what it reads
+    for a plain copy of known size), or None when the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(wl, seconds: float):
@@ -161,7 +190,7 @@ def main():
                        "p99": round(float(np.percentile(lat_us, 99)), 2),
                        "iters": args.latency_iters, "call": "pfsm_scan (synchronous)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "dfa_scan_kernel", "kernel_avg_us": round(kern_avg_s * 1e6, 3),
                      "alg_bytes_per_launch": int(alg_bytes)},
         "wall_s_timed": round(wall, 4),
