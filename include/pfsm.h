@@ -150,7 +150,7 @@ int pfsm_add_pattern(pfsm_t *h, const pfsm_nfa_desc *pattern, void *hip_stream);
 int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream);
 
 /* Scan n bytes of device memory and report every match (Section III.B).
- *   d_input    device pointer to n bytes (any alignment); n in [0, 2^31).
+ *   d_input    device pointer to n bytes (any alignment); n in [0, 2^31 - 16].
  *   d_out      device array of `cap` pfsm_match_t, written in ascending
  *              (start, end, label) order.
  *   n_matches  host pointer, receives the total number of matches.

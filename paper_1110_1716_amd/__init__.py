@@ -238,15 +238,50 @@ def pfsm_scan_async(h: Pfsm, x, out, d_n_matches, stream=None) -> None:
                                           d_n_matches.data_ptr(), _stream_ptr(stream)))
 
 
-def pfsm_scan_batch(handles, data, stream_off, stream_automaton, out, match_off, stream=None) -> int:
-    """Scan concatenated streams; returns the grand total (see include/pfsm.h)."""
+def pfsm_scan_batch(handles, data, stream_off, stream_automaton, out=None, match_off=None, stream=None,
+                    cap: Optional[int] = None):
+    """Scan many streams, each against one of ``handles``, in one call.
+
+    ``data``: 1-D uint8 CUDA tensor holding every stream; ``stream_off``:
+    int64 CUDA tensor [n_streams + 1] of byte offsets into it;
+    ``stream_automaton``: int32 CUDA tensor [n_streams] of indices into
+    ``handles``.  Returns (n_matches, out[:n_matches], match_off): matches
+    grouped by stream in stream order, positions relative to each stream's
+    first byte, group g at out[match_off[g]:match_off[g + 1]].  With
+    ``out=None`` an output of ``cap`` rows is allocated and grown once on
+    overflow.
+    """
+    import torch
+    _check_input(data)
+    n_streams = stream_automaton.numel()
+    for t, dt, name in ((stream_off, torch.int64, "stream_off"), (stream_automaton, torch.int32, "stream_automaton")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.dim() == 1 and t.is_contiguous()):
+            raise PfsmError(PFSM_EINVAL, f"{name} must be a contiguous 1-D {dt} CUDA tensor")
+    if stream_off.numel() != n_streams + 1:
+        raise PfsmError(PFSM_EINVAL, "stream_off must have n_streams + 1 entries")
     lib = load_library()
+    st = _stream_ptr(stream)
+    if match_off is None:
+        match_off = torch.empty(n_streams + 1, dtype=torch.int64, device=data.device)
+    auto = out is None
+    if auto:
+        cap = cap if cap is not None else data.numel() // 16 + 1024
+        out = torch.empty((cap, 3), dtype=torch.int32, device=data.device)
+    _check_out(out)
     arr = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
     n = ctypes.c_int64()
-    _check(lib.pfsm_scan_batch(arr, len(handles), data.data_ptr(), stream_off.data_ptr(),
-                               stream_automaton.data_ptr(), stream_automaton.numel(), out.data_ptr(),
-                               out.shape[0], match_off.data_ptr(), ctypes.byref(n), _stream_ptr(stream)))
-    return n.value
+
+    def call(o):
+        return lib.pfsm_scan_batch(arr, len(handles), data.data_ptr(), stream_off.data_ptr(),
+                                   stream_automaton.data_ptr(), n_streams, o.data_ptr(), o.shape[0],
+                                   match_off.data_ptr(), ctypes.byref(n), st)
+
+    rc = call(out)
+    if rc == PFSM_EOVERFLOW and auto:
+        out = torch.empty((n.value, 3), dtype=torch.int32, device=data.device)
+        rc = call(out)
+    _check(rc)
+    return n.value, out[:n.value], match_off
 
 
 def pfsm_last_stats(h: Pfsm, stream=None) -> dict:

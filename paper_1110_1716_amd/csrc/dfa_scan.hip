@@ -65,8 +65,15 @@ struct DfaCtx {
     int32_t sl32 = 0;
     int64_t wbase = 0;    // current window
     int staged = 0;       // bytes staged from wbase (at most RING)
-    int64_t seg_lo = 0;
-    int32_t n32 = 0;
+    int64_t seg_lo = 0;   // the segment's first start (shifted position)
+    int32_t n32 = 0;      // end of the stream (shifted position)
+    // The stream being scanned: positions inside the kernel are shifted by
+    // dsh = the stream's offset from the 16-byte boundary below it, so that
+    // position p is byte p of the aligned base xa (reported positions are
+    // p - dsh).
+    const uint8_t *xa = nullptr;
+    int64_t nP = 0;
+    int32_t dsh = 0;
     long long T = 0, X = 0, L = 0, M = 0;
 
     static constexpr bool kResident = ENC == kEnc8 || ENC == kEnc8D || ENC == kEnc16;
@@ -149,7 +156,7 @@ struct DfaCtx {
             if (slot + cnt <= MC) {
                 for (int l = 0; l < cnt; ++l) {
                     mkey[slot + l] = ((uint32_t)(start - seg_lo) << 16) | (uint32_t)((k + l) & 0xffff);
-                    mend[slot + l] = end;
+                    mend[slot + l] = end - dsh;
                     mlab[slot + l] = lab_at(lo + l);
                 }
             } else {
@@ -171,7 +178,7 @@ struct DfaCtx {
     __device__ __forceinline__ uint4 chunk(int64_t p) {
         if (staged_at(p)) return *reinterpret_cast<const uint4 *>(xs + ((p - sl) & (RING - 1)));
         ++L;
-        return load_granule(a.x, p);
+        return load_granule(xa, p);
     }
 };
 
@@ -204,7 +211,7 @@ __device__ __forceinline__ bool drain_round(DfaCtx<ENC, kId> &c, QEnt *q, int &q
         const int64_t c0 = (int64_t)(e[j].pos & ~15);
         const bool go = alive[j] && (!kStagedOnly || c.staged_at(c0));
         ch[j] = go ? c.chunk(c0) : make_uint4(0, 0, 0, 0);
-        const int64_t end = c0 + 16 < c.a.n ? c0 + 16 : c.a.n;
+        const int64_t end = c0 + 16 < c.nP ? c0 + 16 : c.nP;
         steps[j] = go ? (int)(end - e[j].pos) : 0;  // symbols left in this chunk
     }
     // t[j]: target of the walk's next symbol (-1: none), looked up a step ahead.
@@ -313,19 +320,19 @@ template <int ENC, bool kId>
 __device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32_t i, bool write, long long at) {
     const DfaArgs &a = c.a;
     long long cnt = 0;
-    int s = c.first_state(a.x[i]);
+    int s = c.first_state(c.xa[i]);
     int32_t pos = i;
     while (s >= 0) {
         for (int l = c.lab_lo(s); l < c.lab_lo(s + 1); ++l, ++cnt) {
             if (write && at + cnt < a.cap) {
                 MatchOut *p = &a.out[at + cnt];
-                p->start = i;
-                p->end = pos;
+                p->start = i - c.dsh;
+                p->end = pos - c.dsh;
                 p->label = c.lab_at(l);
             }
         }
         if (++pos >= c.n32) break;
-        const int sy = c.sym(a.x[pos]);
+        const int sy = c.sym(c.xa[pos]);
         s = sy < 0 ? -1 : c.live(c.tab(s, sy));
     }
     return cnt;
@@ -379,14 +386,14 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     __shared__ int mn, ovf, sp_n, seg_s, last_s;
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
-    __shared__ long long ex_s;
+    __shared__ long long ex_s, base_s;
     __shared__ unsigned epoch_s;
+    __shared__ int nsegs_s, segbase_s;
 
     const int tid = threadIdx.x;
     const int wv = tid >> 6;
     const int lane = lane_id();
     const int b = blockIdx.x;
-    const int32_t n32 = (int32_t)a.n;
     uint8_t *ring = lds + wv * RING;
     uint32_t *lst = reinterpret_cast<uint32_t *>(lds + a.off_list) + wv * kDfaList;
     QEnt *spill = reinterpret_cast<QEnt *>(a.spill) + (int64_t)b * kDfaSpill;
@@ -394,10 +401,26 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     if (tid == 0) {
         seg_s = take_ticket(a.ctl);
         epoch_s = lb_epoch(a.ctl);
+        // Batches: this launch's segment count, list and output base live on
+        // the device (written by the planning kernels).
+        nsegs_s = a.plan.n_segs_dev ? *a.plan.n_segs_dev : a.n_segs;
+        segbase_s = a.plan.seg_base_dev ? *a.plan.seg_base_dev : 0;
+        base_s = a.plan.base_dev ? *a.plan.base_dev : 0;
         mn = 0;
         ovf = 0;
         sp_n = 0;
     }
+    __syncthreads();
+    const int n_segs = nsegs_s;
+    if (seg_s >= n_segs) {
+        // Nothing to scan: only the launch's bookkeeping remains.
+        if (n_segs == 0 && b == 0 && tid == 0) *a.total = base_s;
+        if (tid == 0) a.bstats[4 * b] = a.bstats[4 * b + 1] = a.bstats[4 * b + 2] = a.bstats[4 * b + 3] = 0;
+        finish_launch<NT>(a.ctl, a.lb, a.lb_cap, &last_s);
+        return;
+    }
+    const int seg_base = segbase_s;
+    const long long out_base = base_s;
     // Tables into LDS: every load of a thread is issued before its stores.
     if (tid < 256) {
         const int f = a.first[tid];
@@ -429,28 +452,40 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     const unsigned epoch = epoch_s;
 
     DfaCtx<ENC, kId> c{a, ring, f16_s, slot_s, b2s_s, flags_s, laboff_s, lab_s, tab_s, mkey, mend, mlab, &mn, &ovf};
-    c.n32 = n32;
     QEnt *q = qall + wv * QW;
     int qcount = 0;
 
-    auto fetch = [&](int64_t wb) __attribute__((always_inline)) {
-        const int64_t p = wb + 16 * lane;
-        return p < a.n ? load_granule(a.x, p) : make_uint4(0, 0, 0, 0);
-    };
-
     for (;;) {
         const int sg = seg_s;
-        if (sg >= a.n_segs) break;
-        const int64_t seg_lo = (int64_t)sg * a.seg;
-        const int64_t seg_hi = seg_lo + a.seg < a.n ? seg_lo + a.seg : a.n;
-        // The wave's slice of the segment: a multiple of 16 bytes per wave.
-        const int64_t per = ((seg_hi - seg_lo + 16 * kDfaWaves - 1) / (16 * kDfaWaves)) * 16;
-        int64_t sl = seg_lo + per * wv;
-        const int64_t sh = sl + per < seg_hi ? sl + per : seg_hi;
-        if (sl > seg_hi) sl = seg_hi;
+        if (sg >= n_segs) break;
+        // The segment's stream and its range of starts (stream positions).
+        const uint8_t *sx;
+        int64_t sn, seg_lo;
+        int stream;
+        seg_resolve(a.plan, a.x, a.n, a.seg, sg, seg_base, sx, sn, seg_lo, stream);
+        const int64_t seg_hi = seg_lo + a.seg < sn ? seg_lo + a.seg : sn;
+        // Shifted positions: p = stream position + dsh, bytes of xa.
+        const int dsh = (int)(reinterpret_cast<uintptr_t>(sx) & 15);
+        c.xa = sx - dsh;
+        c.dsh = dsh;
+        c.nP = sn + dsh;
+        c.n32 = (int32_t)c.nP;
+        const int32_t n32 = c.n32;
+        const int64_t own_lo = seg_lo + dsh, own_hi = seg_hi + dsh;
+        const int64_t s0 = own_lo & ~(int64_t)15;
+        // The wave's slice: a multiple of 16 bytes per wave, owning the
+        // starts of [max(sl, own_lo), sh).
+        const int64_t per = ((own_hi - s0 + 16 * kDfaWaves - 1) / (16 * kDfaWaves)) * 16;
+        int64_t sl = s0 + per * wv;
+        const int64_t sh = sl + per < own_hi ? sl + per : own_hi;
+        if (sl > own_hi) sl = own_hi;
+        auto fetch = [&](int64_t wb) __attribute__((always_inline)) {
+            const int64_t p = wb + 16 * lane;
+            return p < c.nP ? load_granule(c.xa, p) : make_uint4(0, 0, 0, 0);
+        };
         uint4 cur = sl < sh ? fetch(sl) : make_uint4(0, 0, 0, 0);
-        uint4 nxt = sl < sh && sl + WIN < a.n ? fetch(sl + WIN) : make_uint4(0, 0, 0, 0);
-        c.seg_lo = seg_lo;
+        uint4 nxt = sl < sh && sl + WIN < c.nP ? fetch(sl + WIN) : make_uint4(0, 0, 0, 0);
+        c.seg_lo = own_lo;
         c.sl = sl;
         c.sl32 = (int32_t)sl;
         const long long m_before = c.M;
@@ -461,14 +496,14 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             const int rb = (int)((wb - sl) & (RING - 1));
             *reinterpret_cast<uint4 *>(ring + ((rb + WIN) & (RING - 1)) + 16 * lane) = nxt;
             const uint4 after = nxt;
-            if (wb + WIN < sh && wb + 2 * WIN < a.n) nxt = fetch(wb + 2 * WIN);
+            if (wb + WIN < sh && wb + 2 * WIN < c.nP) nxt = fetch(wb + 2 * WIN);
             __builtin_amdgcn_wave_barrier();
             c.wbase = wb;
-            const int64_t rest = a.n - wb;
+            const int64_t rest = c.nP - wb;
             c.staged = (int)(rest < RING ? rest : RING);
 
             // The staged pair ends at lim.
-            const int32_t lim = (int32_t)(rest < RING ? a.n : wb + RING);
+            const int32_t lim = (int32_t)(rest < RING ? c.nP : wb + RING);
 
             // Walks parked at the end of the previous window continue.
             {
@@ -486,12 +521,13 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
                 }
             }
 
-            // Starts owned in this window: [wb, min(wb + WIN, sh)).
-            const int64_t own_end = wb + WIN < sh ? wb + WIN : sh;
-            const int64_t nv64 = own_end - (wb + 16 * lane);
-            const int nvalid = nv64 <= 0 ? 0 : (nv64 >= 16 ? 16 : (int)nv64);
-            const unsigned vmask = nvalid >= 16 ? 0xffffu : ((1u << nvalid) - 1u);
-            c.T += nvalid;
+            // Starts owned by this lane: its 16 bytes within [own_lo, sh).
+            const int64_t lb = wb + 16 * lane;
+            const int64_t hi64 = sh - lb, lo64 = own_lo - lb;
+            const int khi = hi64 <= 0 ? 0 : (hi64 >= 16 ? 16 : (int)hi64);
+            const int klo = lo64 <= 0 ? 0 : (lo64 >= 16 ? 16 : (int)lo64);
+            const unsigned vmask = ((1u << khi) - 1u) & ~((1u << klo) - 1u);
+            c.T += __popc(vmask);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 // Symbol one for 8 starts per lane (q0's row by byte), then the
@@ -558,11 +594,17 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             const long long ex = lookback(a.lb, sg, epoch, mine_m);
             if (lane == 0) {
                 ex_s = ex;
-                if (sg == a.n_segs - 1) *a.total = ex + mine_m;
+                const long long at = out_base + ex;
+                if (sg == n_segs - 1) *a.total = at + mine_m;
+                if (stream >= 0) {
+                    // The stream's range in this launch's output.
+                    if (seg_lo == 0) a.plan.stream_lo[stream] = at;
+                    if (seg_hi == sn) a.plan.stream_hi[stream] = at + mine_m;
+                }
             }
         }
         __syncthreads();
-        const long long at0 = ex_s;
+        const long long at0 = out_base + ex_s;
         if (!ovf) {
             // Rank of every buffered match in (start, end, label) order:
             // bucket by start offset / 64 (histogram, scan, scatter), then
@@ -611,16 +653,16 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
                 const long long at = at0 + rank;
                 if (at < a.cap) {
                     MatchOut *p = &a.out[at];
-                    p->start = (int32_t)(seg_lo + (mk >> 16));
+                    p->start = (int32_t)(seg_lo + (mk >> 16));  // stream position
                     p->end = mend[e];
                     p->label = mlab[e];
                 }
             }
         } else {
             long long run = at0;
-            for (int64_t c0 = seg_lo; c0 < seg_hi; c0 += NT) {
+            for (int64_t c0 = own_lo; c0 < own_hi; c0 += NT) {
                 const int64_t i = c0 + tid;
-                const bool own = i < seg_hi;
+                const bool own = i < own_hi;
                 const long long cnt = own ? walk_start(c, (int32_t)i, false, 0) : 0;
                 long long ctot;
                 const long long ex = block_excl_scan<NT>(cnt, red, &ctot);

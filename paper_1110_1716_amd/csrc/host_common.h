@@ -71,6 +71,10 @@ struct DevBuf {
     }
 };
 
+// Longest stream: positions, shifted by up to 15 bytes for alignment, are
+// int32 inside the kernels.
+constexpr int64_t kMaxStream = (1ll << 31) - 16;
+
 // Segments a launch may have: inputs are below 2^31 bytes and a segment
 // holds at least min(n / grid, 64 KiB) bytes.
 constexpr int kMaxSegs = 32768;
@@ -155,6 +159,21 @@ struct WorkspacePool {
         return r;
     }
 };
+
+// Grow the look-back words of `w` to at least `need` (synchronises the
+// stream; the new words are clear, so they carry no epoch in use).
+inline int grow_lb(Workspace *w, int need) {
+    if (need <= w->lb_cap) return PFSM_OK;
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    unsigned long long *nb = nullptr;
+    HIP_TRY(hipMalloc(&nb, sizeof(unsigned long long) * need));
+    HIP_TRY(hipMemset(nb, 0, sizeof(unsigned long long) * need));
+    HIP_TRY(hipDeviceSynchronize());
+    if (w->lb) HIP_TRY(hipFree(w->lb));
+    w->lb = nb;
+    w->lb_cap = need;
+    return PFSM_OK;
+}
 
 // The scan kernels read 16-byte granules and need a 16-byte aligned input:
 // a misaligned input is first copied (in stream order) into a buffer of the

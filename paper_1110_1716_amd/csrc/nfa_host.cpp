@@ -419,12 +419,11 @@ int nfa_grid_blocks(NfaHost *h) { return h->n_blocks; }
 
 WorkspacePool *nfa_pool(NfaHost *h) { return &h->pool; }
 
-int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap, int64_t *d_total,
-                   hipStream_t s) {
+int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
+               int64_t cap, int64_t *d_total, hipStream_t s) {
     Workspace *w;
     int rc = h->pool.get(s, h->n_blocks, &w);
     if (rc) return rc;
-    if ((rc = align_input(w, &x, n, s))) return rc;
     NfaTables *t = h->tab.get();
     // replay scratch sized for the current union
     const int64_t words_front = (int64_t)h->n_blocks * 2 * t->n_states;
@@ -465,17 +464,36 @@ int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64
     a.out = out;
     a.cap = cap;
     a.total = d_total;
-    a.slots = w->slots;
+    a.ctl = w->ctl;
+    a.lb = w->lb;
+    a.lb_cap = w->lb_cap;
     a.bstats = w->bstats;
-    a.n_blocks = h->n_blocks;
-    plan_segments(n, h->n_blocks, kNfaSegMax, &a.seg, &a.n_rounds);
     a.big_front = w->big_front;
     a.big_bits = w->big_bits;
+    int grid = h->n_blocks;
+    if (plan) {
+        a.plan = *plan;
+        a.seg = seg;
+    } else {
+        int rounds;
+        plan_segments(n, h->n_blocks, kNfaSegMax, &a.seg, &rounds);
+        const int64_t n_segs = (n + a.seg - 1) / a.seg;
+        if (n_segs > w->lb_cap)
+            return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)", (long long)n,
+                        (long long)n_segs, w->lb_cap);
+        a.n_segs = (int32_t)n_segs;
+        grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
+    }
     void *args[] = {&a};
-    HIP_TRY(hipLaunchCooperativeKernel(nfa_kernel_fn(), dim3(h->n_blocks), dim3(kNfaThreads), args, 0, s));
-    w->last_grid = h->n_blocks;
+    HIP_TRY(hipLaunchKernel(nfa_kernel_fn(), dim3(grid), dim3(kNfaThreads), args, 0, s));
+    w->last_grid = grid;
     w->scanned = true;
     return PFSM_OK;
+}
+
+int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap, int64_t *d_total,
+                   hipStream_t s) {
+    return nfa_launch(h, x, n, nullptr, 0, out, cap, d_total, s);
 }
 
 }  // namespace pfsmk

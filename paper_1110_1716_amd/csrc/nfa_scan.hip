@@ -1,8 +1,8 @@
 // All-matches NFA scan for gfx950 (Section III.B with epsilon transitions;
 // the NFA case of Section III.C).
 //
-// Persistent cooperative grid of 256-thread workgroups; workgroup b owns the
-// start positions of one contiguous segment per round (lazy data
+// Grid of 256-thread workgroups that take segments from a ticket counter; a
+// workgroup owns the start positions of its segment (lazy data
 // partitioning, Section III.D.2).  For each start i the instance's state set
 // is advanced one symbol at a time (Section III.B steps 3-4), closed under
 // epsilon edges right after each symbol, and every label of every final
@@ -23,7 +23,7 @@
 //   * Matches go to an LDS buffer keyed by (start - segment start, k), k the
 //     instance's match count so far; labels of one symbol are reported in
 //     increasing order, so k orders (end, label) within a start.  Offsets come
-//     from per-workgroup epoch-tagged count slots as in the DFA scan; a
+//     from decoupled look-back over the segment tickets as in the DFA scan; a
 //     segment whose matches overflow the buffer is walked again 256 starts at
 //     a time to count, scan and write.
 #include "scan_common.h"
@@ -62,8 +62,14 @@ struct NfaCtx {
     int32_t *mlab;
     int *mn;
     int *ovf;
-    int64_t seg_lo;
-    int32_t n32;
+    int64_t seg_lo = 0;   // the segment's first start (shifted position)
+    int32_t n32 = 0;      // end of the stream (shifted position)
+    // Positions are shifted by dsh, the stream's offset from the 16-byte
+    // boundary below it: position p is byte p of the aligned base xa, and
+    // reported positions are p - dsh.
+    const uint8_t *xa = nullptr;
+    int64_t nP = 0;
+    int32_t dsh = 0;
     long long T = 0, X = 0, L = 0, M = 0;
 
     // Record one match of the instance started at `start`.  k is the number
@@ -76,7 +82,7 @@ struct NfaCtx {
             const int slot = atomicAdd(mn, 1);
             if (slot < MC) {
                 mkey[slot] = ((uint32_t)(start - seg_lo) << 16) | (uint32_t)(k & 0xffff);
-                mend[slot] = end;
+                mend[slot] = end - dsh;
                 mlab[slot] = label;
             } else {
                 *ovf = 1;
@@ -84,8 +90,8 @@ struct NfaCtx {
         } else if (mode == kWrite) {
             if (at + k < a.cap) {
                 MatchOut *p = &a.out[at + k];
-                p->start = start;
-                p->end = end;
+                p->start = start - dsh;
+                p->end = end - dsh;
                 p->label = label;
             }
         }
@@ -244,7 +250,7 @@ __device__ __forceinline__ int first_two(NfaCtx &c, int c1, int c2, uint32_t (&S
 __device__ __forceinline__ long long walk_lane(NfaCtx &c, int32_t i, int mode, long long at) {
     const NfaArgs &a = c.a;
     int32_t k = 0;
-    const int c1 = a.x[i];
+    const int c1 = c.xa[i];
     const int n1 = c.f1o_s[c1 + 1] - c.f1o_s[c1];
     if (n1 == 0) return 0;
     emit_list(c, mode, a.e1, c.e1o_s[c1], c.e1o_s[c1 + 1], i, i, k, 0, at);
@@ -252,7 +258,7 @@ __device__ __forceinline__ long long walk_lane(NfaCtx &c, int32_t i, int mode, l
     uint32_t S[K];
     int llo, lhi;
     bool ovf;
-    int nS = first_two(c, c1, a.x[i + 1], S, llo, lhi, ovf);
+    int nS = first_two(c, c1, c.xa[i + 1], S, llo, lhi, ovf);
     if (ovf) return -1;
     if (a.pair_on) emit_list(c, mode, a.p_lab, llo, lhi, i, i + 1, k, 0, at);
     else emit_set(c, mode, S, nS, i, i + 1, k, 0, at);
@@ -260,7 +266,7 @@ __device__ __forceinline__ long long walk_lane(NfaCtx &c, int32_t i, int mode, l
     while (nS > 0 && pos < c.n32) {
         uint32_t O[K];
         int nO;
-        if (!nfa_step(a, S, nS, a.x[pos], O, nO)) return -1;
+        if (!nfa_step(a, S, nS, c.xa[pos], O, nO)) return -1;
         emit_set(c, mode, O, nO, i, pos, k, 0, at);
 #pragma unroll
         for (int j = 0; j < K; ++j) S[j] = O[j];
@@ -293,7 +299,7 @@ __device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0
     // sh[0]: next frontier size, sh[1..NT/64]: reduction slots, sh[8]: k
     const NfaArgs &a = c.a;
     const int tid = threadIdx.x;
-    const int c1 = a.x[s];
+    const int c1 = c.xa[s];
     int nF = c.f1o_s[c1 + 1] - c.f1o_s[c1];
     for (int j = tid; j < nF; j += NT) F0[j] = a.f1[c.f1o_s[c1] + j];
     int32_t k = 0;  // tracked by every thread identically
@@ -311,7 +317,7 @@ __device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0
     uint32_t *cur = F0, *nxt = F1;
     int32_t pos = s + 1;
     while (nF > 0 && pos < c.n32) {
-        const int byte = a.x[pos];
+        const int byte = c.xa[pos];
         for (int j = tid; j < nF; j += NT) {
             const NfaRec r = a.rec[cur[j] & kStateMask];
             const int ne = r.n_edges;
@@ -407,9 +413,9 @@ __device__ __forceinline__ void drain_round(NfaCtx &c, Walk *q, int &qcount, Big
     for (int j = 0; j < QK; ++j) {
         if (!alive[j]) continue;
         const int64_t c0 = (int64_t)(e[j].pos & ~15);
-        const uint4 ch = load_granule(a.x, c0);
+        const uint4 ch = load_granule(c.xa, c0);
         ++c.L;
-        const int steps = (int)((c0 + 16 < a.n ? c0 + 16 : a.n) - e[j].pos);
+        const int steps = (int)((c0 + 16 < c.nP ? c0 + 16 : c.nP) - e[j].pos);
         for (int st = 0; st < steps && alive[j]; ++st) {
             uint32_t O[K];
             int nO;
@@ -449,38 +455,52 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     __shared__ int32_t mend[MC];
     __shared__ int32_t mlab[MC];
     __shared__ Big big_s[BC];
-    __shared__ int mn, ovf, nbig;
+    __shared__ int mn, ovf, nbig, seg_s, last_s, nsegs_s, segbase_s;
     __shared__ int sh[16];
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
+    __shared__ long long ex_s, base_s;
     __shared__ unsigned epoch_s;
 
     const int tid = threadIdx.x;
     const int wv = tid >> 6;
+    const int lane = lane_id();
     const int b = blockIdx.x;
-    const int32_t n32 = (int32_t)a.n;
+    if (tid == 0) {
+        seg_s = take_ticket(a.ctl);
+        epoch_s = lb_epoch(a.ctl);
+        nsegs_s = a.plan.n_segs_dev ? *a.plan.n_segs_dev : a.n_segs;
+        segbase_s = a.plan.seg_base_dev ? *a.plan.seg_base_dev : 0;
+        base_s = a.plan.base_dev ? *a.plan.base_dev : 0;
+        mn = 0;
+        ovf = 0;
+        nbig = 0;
+    }
+    __syncthreads();
+    const int n_segs = nsegs_s;
+    if (seg_s >= n_segs) {
+        if (n_segs == 0 && b == 0 && tid == 0) *a.total = base_s;
+        if (tid == 0) a.bstats[4 * b] = a.bstats[4 * b + 1] = a.bstats[4 * b + 2] = a.bstats[4 * b + 3] = 0;
+        finish_launch<NT>(a.ctl, a.lb, a.lb_cap, &last_s);
+        return;
+    }
+    const int seg_base = segbase_s;
+    const long long out_base = base_s;
     if (a.pair_on)
         for (int i = tid; i < 2048; i += NT) pbits_s[i] = a.p_bits[i];
     for (int i = tid; i < 257; i += NT) {
         f1o_s[i] = a.f1_off[i];
         e1o_s[i] = a.e1_off[i];
     }
-    if (tid == 0) {
-        mn = 0;
-        ovf = 0;
-        nbig = 0;
-        epoch_s = first_epoch(a.slots, b);
-    }
     __syncthreads();
-    const unsigned epoch0 = epoch_s;
+    const unsigned epoch = epoch_s;
     const size_t ns = (size_t)a.n_states;
     uint32_t *F0 = a.big_front + (size_t)b * 2 * ns;
     uint32_t *F1 = F0 + ns;
     uint32_t *bits = a.big_bits + (size_t)b * ((ns + 31) / 32);
 
-    NfaCtx c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf, 0, n32};
+    NfaCtx c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf};
     Walk *q = qall + wv * QW;
-    long long base_out = 0;
 
     // Replay every listed start with the whole workgroup.
     auto run_big = [&]() __attribute__((always_inline)) {
@@ -496,24 +516,39 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         __syncthreads();
     };
 
-    for (int r = 0; r < a.n_rounds; ++r) {
-        const int64_t seg_lo = ((int64_t)r * a.n_blocks + b) * a.seg;
-        const int64_t seg_hi = seg_lo + a.seg < a.n ? seg_lo + a.seg : a.n;
-        c.seg_lo = seg_lo;
+    for (;;) {
+        const int sg = seg_s;
+        if (sg >= n_segs) break;
+        const uint8_t *sx;
+        int64_t sn, seg_lo;
+        int stream;
+        seg_resolve(a.plan, a.x, a.n, a.seg, sg, seg_base, sx, sn, seg_lo, stream);
+        const int64_t seg_hi = seg_lo + a.seg < sn ? seg_lo + a.seg : sn;
+        // Shifted positions: p = stream position + dsh, byte p of xa.
+        const int dsh = (int)(reinterpret_cast<uintptr_t>(sx) & 15);
+        c.xa = sx - dsh;
+        c.dsh = dsh;
+        c.nP = sn + dsh;
+        c.n32 = (int32_t)c.nP;
+        const int32_t n32 = c.n32;
+        const int64_t own_lo = seg_lo + dsh, own_hi = seg_hi + dsh;
+        c.seg_lo = own_lo;
         const long long m_before = c.M;
         int qcount = 0;
-        for (int64_t wbase = seg_lo; wbase < seg_hi; wbase += W) {
-            const int64_t wend = wbase + W < seg_hi ? wbase + W : seg_hi;
+        for (int64_t wbase = own_lo & ~(int64_t)15; wbase < own_hi; wbase += W) {
             const int64_t i0 = wbase + 16 * tid;
-            const uint4 mine = i0 < a.n ? load_granule(a.x, i0) : make_uint4(0, 0, 0, 0);
-            const int64_t nv64 = wend - i0;
-            const int nvalid = nv64 <= 0 ? 0 : (nv64 >= 16 ? 16 : (int)nv64);
-            const int tail = (nvalid == 16 && i0 + 16 < a.n) ? a.x[i0 + 16] : 0;
+            const uint4 mine = i0 < c.nP ? load_granule(c.xa, i0) : make_uint4(0, 0, 0, 0);
+            // Starts owned by this thread: its 16 bytes within [own_lo, own_hi).
+            const int64_t hi64 = own_hi - i0, lo64 = own_lo - i0;
+            const int khi = hi64 <= 0 ? 0 : (hi64 >= 16 ? 16 : (int)hi64);
+            const int klo = lo64 <= 0 ? 0 : (lo64 >= 16 ? 16 : (int)lo64);
+            const unsigned vmask = ((1u << khi) - 1u) & ~((1u << klo) - 1u);
+            const int tail = ((vmask >> 15) & 1u) && i0 + 16 < c.nP ? c.xa[i0 + 16] : 0;
             for (int k = 0; k < 16; ++k) {
                 bool push = false;
                 Walk ent;
                 ent.n = 0;
-                if (k < nvalid) {
+                if ((vmask >> k) & 1u) {
                     const int32_t i = (int32_t)(i0 + k);
                     const int c1 = byte_of(mine, k);
                     ++c.T;
@@ -569,12 +604,23 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         __syncthreads();
         if (!ovf) run_big();
 
-        // Offsets: this round's count, the peers' counts, placement.
+        // The segment's count, its offset by look-back, and placement.
         const long long mine_m = block_sum<NT>(c.M - m_before, red);
-        long long round_total;
-        const long long excl =
-            grid_prefix<NT>(a.slots, a.n_blocks, b, (epoch0 + r) & kEpochMask, mine_m, red, &round_total);
-        const long long at0 = base_out + excl;
+        if (tid == 0) seg_s = take_ticket(a.ctl);  // the next segment, requested early
+        if (wv == 0) {
+            const long long ex = lookback(a.lb, sg, epoch, mine_m);
+            if (lane == 0) {
+                ex_s = ex;
+                const long long at = out_base + ex;
+                if (sg == n_segs - 1) *a.total = at + mine_m;
+                if (stream >= 0) {
+                    if (seg_lo == 0) a.plan.stream_lo[stream] = at;
+                    if (seg_hi == sn) a.plan.stream_hi[stream] = at + mine_m;
+                }
+            }
+        }
+        __syncthreads();
+        const long long at0 = out_base + ex_s;
         if (!ovf) {
             const int m = mn;
             for (int e = tid; e < m; e += NT) {
@@ -595,7 +641,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                 const long long at = at0 + rank;
                 if (at < a.cap) {
                     MatchOut *p = &a.out[at];
-                    p->start = (int32_t)(seg_lo + (mk >> 16));
+                    p->start = (int32_t)(seg_lo + (mk >> 16));  // stream position
                     p->end = mend[e];
                     p->label = mlab[e];
                 }
@@ -603,9 +649,9 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         } else {
             // Dense segment: count, scan and write 256 starts at a time.
             long long run = at0;
-            for (int64_t c0 = seg_lo; c0 < seg_hi; c0 += NT) {
+            for (int64_t c0 = own_lo; c0 < own_hi; c0 += NT) {
                 const int64_t i = c0 + tid;
-                const bool own = i < seg_hi;
+                const bool own = i < own_hi;
                 long long cnt = own ? walk_lane(c, (int32_t)i, kCount, 0) : 0;
                 // starts whose sets outgrow K: counted by the whole workgroup
                 for (;;) {
@@ -634,7 +680,6 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                 run += ctot;
             }
         }
-        base_out += round_total;
         __syncthreads();
         if (tid == 0) {
             mn = 0;
@@ -643,13 +688,13 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         }
         __syncthreads();
     }
-    if (b == 0 && tid == 0) *a.total = base_out;
     long long st4[4] = {c.T, c.X, c.L, c.M};
     block_sum4<NT>(st4, red4);
     if (tid == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) a.bstats[4 * b + k] = st4[k];
     }
+    finish_launch<NT>(a.ctl, a.lb, a.lb_cap, &last_s);
 }
 
 }  // namespace

@@ -38,6 +38,20 @@ constexpr unsigned long long kLbValMask = (1ull << 40) - 1;
 constexpr unsigned kLbEpochMod = (1u << 22) - 1;  // epochs in use: 1 .. kLbEpochMod
 constexpr int kLbAgg = 1, kLbIncl = 2;
 
+// Segments of a batch launch (stream_off == nullptr: one stream, x[0, n)).
+// x holds every stream; the launch's segments, their streams and the output
+// base are written on the device by the planning kernels.
+struct SegPlan {
+    const int64_t *stream_off;  // [n_streams + 1] byte offsets into x
+    const int32_t *seg_stream;  // stream of each segment, from *seg_base_dev on
+    const int32_t *seg_first;   // [n_streams] first segment of each stream in its launch
+    const int32_t *n_segs_dev;  // segments of this launch
+    const int32_t *seg_base_dev;
+    const int64_t *base_dev;    // output index of this launch's first match
+    int64_t *stream_lo;         // [n_streams] each stream's range in the output
+    int64_t *stream_hi;
+};
+
 struct MatchOut {
     int32_t start, end, label;
 };
@@ -90,7 +104,8 @@ struct DfaArgs {
     ScanCtl *ctl;
     unsigned long long *lb;     // [lb_cap] look-back words, one per segment
     int32_t lb_cap;
-    int32_t n_segs;             // segments of this launch
+    int32_t n_segs;             // segments of this launch (single stream)
+    SegPlan plan;               // batches
     long long *bstats;          // [gridDim.x * 4] T, X, long walks, matches
     void *spill;                // [gridDim.x * kDfaSpill] walks parked out of LDS
     int64_t seg;                // bytes per segment (multiple of 16)
@@ -164,14 +179,17 @@ struct NfaArgs {
     MatchOut *out;
     int64_t cap;
     int64_t *total;
-    unsigned long long *slots;  // [n_blocks]
-    long long *bstats;          // [n_blocks * 4]
+    ScanCtl *ctl;
+    unsigned long long *lb;     // [lb_cap] look-back words, one per segment
+    int32_t lb_cap;
+    int32_t n_segs;
+    SegPlan plan;
+    long long *bstats;          // [gridDim.x * 4]
     int64_t seg;
-    int32_t n_blocks, n_rounds;
     // per-workgroup replay scratch: two frontiers of n_states entries and a
     // bitset of n_states bits (all clear between uses)
-    uint32_t *big_front;        // [n_blocks * 2 * n_states]
-    uint32_t *big_bits;         // [n_blocks * ((n_states + 31) / 32)]
+    uint32_t *big_front;        // [gridDim.x * 2 * n_states]
+    uint32_t *big_bits;         // [gridDim.x * ((n_states + 31) / 32)]
 };
 
 const void *nfa_kernel_fn();

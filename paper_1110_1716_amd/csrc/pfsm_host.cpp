@@ -7,11 +7,14 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "host_common.h"
 #include "pfsm_dev.h"
 #include "pfsm_nfa.h"
@@ -372,28 +375,17 @@ int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream) {
     return dfa_upload_caches(h, s);
 }
 
-int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
-                    int64_t *d_n_matches, void *hip_stream) {
-    if (!h) return fail(PFSM_EINVAL, "NULL handle");
-    if (n < 0 || n >= (1ll << 31)) return fail(PFSM_EINVAL, "n must be in [0, 2^31)");
-    if (cap < 0) return fail(PFSM_EINVAL, "cap must be >= 0");
-    if (!d_n_matches) return fail(PFSM_EINVAL, "d_n_matches is NULL");
-    if (n > 0 && !d_input) return fail(PFSM_EINVAL, "d_input is NULL");
-    if (cap > 0 && !d_out) return fail(PFSM_EINVAL, "d_out is NULL");
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (n == 0) {
-        HIP_TRY(launch_write_zero(d_n_matches, s));
-        return PFSM_OK;
-    }
-    if (h->kind == 1)
-        return nfa_scan_async(h->nfa.get(), d_input, n, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, s);
+// One launch of the DFA scan kernel: a single stream (plan == nullptr) or the
+// segments of a batch plan.
+static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
+                      int64_t cap, int64_t *d_total, hipStream_t s) {
     Workspace *w;
     int rc = h->pool.get(s, h->n_blocks, &w);
     if (rc) return rc;
-    if ((rc = align_input(w, &d_input, n, s))) return rc;
+    if (!w->spill) HIP_TRY(hipMalloc(&w->spill, (size_t)h->n_blocks * kDfaSpill * 16));
     DfaArgs a;
     std::memset(&a, 0, sizeof a);
-    a.x = d_input;
+    a.x = x;
     a.n = n;
     a.tbl = h->d_tbl.p;
     a.res = h->d_res.p;
@@ -407,22 +399,28 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
     a.flags = h->d_flags.as<uint8_t>();
     a.lab_off = h->d_lab_off.as<int32_t>();
     a.lab = h->d_lab.as<int32_t>();
-    a.out = reinterpret_cast<MatchOut *>(d_out);
+    a.out = out;
     a.cap = cap;
-    a.total = d_n_matches;
-    if (!w->spill) HIP_TRY(hipMalloc(&w->spill, (size_t)h->n_blocks * kDfaSpill * 16));
+    a.total = d_total;
     a.ctl = w->ctl;
     a.lb = w->lb;
     a.lb_cap = w->lb_cap;
     a.bstats = w->bstats;
     a.spill = w->spill;
-    int rounds;
-    plan_segments(n, h->n_blocks, kDfaSegMax, &a.seg, &rounds);
-    const int64_t n_segs = (n + a.seg - 1) / a.seg;
-    if (n_segs > w->lb_cap) return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)",
-                                        (long long)n, (long long)n_segs, w->lb_cap);
-    a.n_segs = (int32_t)n_segs;
-    const int grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
+    int grid = h->n_blocks;
+    if (plan) {
+        a.plan = *plan;
+        a.seg = seg;
+    } else {
+        int rounds;
+        plan_segments(n, h->n_blocks, kDfaSegMax, &a.seg, &rounds);
+        const int64_t n_segs = (n + a.seg - 1) / a.seg;
+        if (n_segs > w->lb_cap)
+            return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)", (long long)n,
+                        (long long)n_segs, w->lb_cap);
+        a.n_segs = (int32_t)n_segs;
+        grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
+    }
     a.off_flags = h->off_flags;
     a.off_laboff = h->off_laboff;
     a.off_lab = h->off_lab;
@@ -436,6 +434,24 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
     w->last_grid = grid;
     w->scanned = true;
     return PFSM_OK;
+}
+
+int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
+                    int64_t *d_n_matches, void *hip_stream) {
+    if (!h) return fail(PFSM_EINVAL, "NULL handle");
+    if (n < 0 || n > kMaxStream) return fail(PFSM_EINVAL, "n must be in [0, 2^31 - 16]");
+    if (cap < 0) return fail(PFSM_EINVAL, "cap must be >= 0");
+    if (!d_n_matches) return fail(PFSM_EINVAL, "d_n_matches is NULL");
+    if (n > 0 && !d_input) return fail(PFSM_EINVAL, "d_input is NULL");
+    if (cap > 0 && !d_out) return fail(PFSM_EINVAL, "d_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (n == 0) {
+        HIP_TRY(launch_write_zero(d_n_matches, s));
+        return PFSM_OK;
+    }
+    if (h->kind == 1)
+        return nfa_scan_async(h->nfa.get(), d_input, n, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, s);
+    return dfa_launch(h, d_input, n, nullptr, 0, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, s);
 }
 
 int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
@@ -456,12 +472,156 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
     return PFSM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device buffers of batched scans on one stream (kept for the process).
+struct BatchWs {
+    int32_t *seg_first = nullptr, *seg_stream = nullptr, *n_segs = nullptr, *seg_base = nullptr;
+    int64_t *bases = nullptr, *stream_lo = nullptr, *stream_hi = nullptr;
+    MatchOut *stage = nullptr;
+    BatchInfo *info = nullptr, *h_info = nullptr;  // h_info: pinned
+    int64_t c_first = 0, c_seg = 0, c_nsegs = 0, c_base = 0, c_bases = 0, c_lo = 0, c_hi = 0, c_stage = 0;
+};
+
+std::mutex g_batch_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<BatchWs>> g_batch;
+
+// Replace *p by a buffer of at least `need` elements when it holds fewer
+// (the stream is synchronised first; contents are not kept).
+template <typename T>
+int grow(T **p, int64_t *cap, int64_t need, hipStream_t s) {
+    if (need <= *cap) return PFSM_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (*p) HIP_TRY(hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    HIP_TRY(hipMalloc(p, sizeof(T) * (size_t)need));
+    *cap = need;
+    return PFSM_OK;
+}
+
+int batch_ws(hipStream_t s, BatchWs **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto &slot = g_batch[{dev, s}];
+    if (!slot) {
+        auto w = std::make_unique<BatchWs>();
+        HIP_TRY(hipMalloc(&w->info, sizeof(BatchInfo)));
+        HIP_TRY(hipHostMalloc(&w->h_info, sizeof(BatchInfo), hipHostMallocDefault));
+        slot = std::move(w);
+    }
+    *out = slot.get();
+    return PFSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
                     const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
                     int64_t *d_match_off, int64_t *n_matches, void *hip_stream) {
-    (void)hs; (void)n_automata; (void)d_data; (void)d_stream_off; (void)d_stream_automaton;
-    (void)n_streams; (void)d_out; (void)cap; (void)d_match_off; (void)n_matches; (void)hip_stream;
-    return fail(PFSM_ENOSYS, "pfsm_scan_batch is not available yet");
+    if (!hs || !n_matches || !d_match_off) return fail(PFSM_EINVAL, "NULL argument");
+    if (n_automata < 1 || n_automata > kMaxBatchAutomata)
+        return fail(PFSM_EINVAL, "n_automata must be in [1, %d]", kMaxBatchAutomata);
+    for (int a = 0; a < n_automata; ++a)
+        if (!hs[a]) return fail(PFSM_EINVAL, "handle %d is NULL", a);
+    if (n_streams < 0) return fail(PFSM_EINVAL, "n_streams must be >= 0");
+    if (n_streams > 0 && (!d_stream_off || !d_stream_automaton || !d_data))
+        return fail(PFSM_EINVAL, "stream arrays are NULL");
+    if (cap < 0) return fail(PFSM_EINVAL, "cap must be >= 0");
+    if (cap > 0 && !d_out) return fail(PFSM_EINVAL, "d_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    BatchWs *bw;
+    int rc = batch_ws(s, &bw);
+    if (rc) return rc;
+    const int64_t ns = std::max(n_streams, 1);
+    if ((rc = grow(&bw->seg_first, &bw->c_first, ns, s))) return rc;
+    if ((rc = grow(&bw->stream_lo, &bw->c_lo, ns, s))) return rc;
+    if ((rc = grow(&bw->stream_hi, &bw->c_hi, ns, s))) return rc;
+    if ((rc = grow(&bw->n_segs, &bw->c_nsegs, n_automata, s))) return rc;
+    if ((rc = grow(&bw->seg_base, &bw->c_base, n_automata, s))) return rc;
+    if ((rc = grow(&bw->bases, &bw->c_bases, n_automata + 1, s))) return rc;
+    if ((rc = grow(&bw->stage, &bw->c_stage, std::max<int64_t>(cap, 1), s))) return rc;
+    if ((rc = grow(&bw->seg_stream, &bw->c_seg, 4 * ns + 4096, s))) return rc;
+
+    // The workspace of every automaton on this stream (look-back words, ...).
+    std::vector<Workspace *> ws(n_automata);
+    for (int a = 0; a < n_automata; ++a) {
+        pfsm_t *h = hs[a];
+        const int nb = h->kind == 1 ? nfa_grid_blocks(h->nfa.get()) : h->n_blocks;
+        if ((rc = (h->kind == 1 ? nfa_pool(h->nfa.get()) : &h->pool)->get(s, nb, &ws[a]))) return rc;
+    }
+    for (int attempt = 0;; ++attempt) {
+        int lb_cap = 1 << 30;
+        for (Workspace *w : ws) lb_cap = std::min(lb_cap, w->lb_cap);
+        BatchPlanArgs p{};
+        p.stream_off = d_stream_off;
+        p.stream_aut = d_stream_automaton;
+        p.n_streams = n_streams;
+        p.n_aut = n_automata;
+        p.seg = kBatchSeg;
+        p.max_stream = kMaxStream;
+        p.seg_first = bw->seg_first;
+        p.seg_stream = bw->seg_stream;
+        p.n_segs = bw->n_segs;
+        p.seg_base = bw->seg_base;
+        p.bases = bw->bases;
+        p.stream_lo = bw->stream_lo;
+        p.stream_hi = bw->stream_hi;
+        p.info = bw->info;
+        p.seg_cap = (int32_t)std::min<int64_t>(bw->c_seg, 1 << 30);
+        p.lb_cap = lb_cap;
+        HIP_TRY(launch_batch_plan(p, s));
+        // One launch per automaton, each after the previous one's matches.
+        for (int a = 0; a < n_automata; ++a) {
+            SegPlan sp{};
+            sp.stream_off = d_stream_off;
+            sp.seg_stream = bw->seg_stream;
+            sp.seg_first = bw->seg_first;
+            sp.n_segs_dev = bw->n_segs + a;
+            sp.seg_base_dev = bw->seg_base + a;
+            sp.base_dev = bw->bases + a;
+            sp.stream_lo = bw->stream_lo;
+            sp.stream_hi = bw->stream_hi;
+            pfsm_t *h = hs[a];
+            rc = h->kind == 1 ? nfa_launch(h->nfa.get(), d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage,
+                                           bw->bases + a + 1, s)
+                              : dfa_launch(h, d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage, bw->bases + a + 1, s);
+            if (rc) return rc;
+        }
+        BatchGatherArgs g{};
+        g.n_streams = n_streams;
+        g.stream_lo = bw->stream_lo;
+        g.stream_hi = bw->stream_hi;
+        g.match_off = d_match_off;
+        g.stage = bw->stage;
+        g.stage_cap = bw->c_stage;
+        g.out = reinterpret_cast<MatchOut *>(d_out);
+        g.cap = cap;
+        g.info = bw->info;
+        HIP_TRY(launch_batch_gather(g, s));
+        HIP_TRY(hipMemcpyAsync(bw->h_info, bw->info, sizeof(BatchInfo), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const BatchInfo info = *bw->h_info;
+        if (info.err == 1) return fail(PFSM_EINVAL, "a stream names an automaton outside [0, %d)", n_automata);
+        if (info.err) return fail(PFSM_EINVAL, "stream offsets must not decrease and streams must be at most 2^31 - 16 bytes");
+        const bool more_segs = info.total_segs > p.seg_cap, more_lb = info.max_segs > lb_cap;
+        if (!more_segs && !more_lb) {
+            *n_matches = info.total;
+            if (info.total > cap)
+                return fail(PFSM_EOVERFLOW, "%lld matches, capacity %lld", (long long)info.total, (long long)cap);
+            return PFSM_OK;
+        }
+        if (attempt > 0) return fail(PFSM_EHIP, "batch plan did not fit after growing its buffers");
+        if (more_segs && (rc = grow(&bw->seg_stream, &bw->c_seg, (int64_t)info.total_segs + 4096, s))) return rc;
+        if (more_lb)
+            for (Workspace *w : ws)
+                if ((rc = grow_lb(w, info.max_segs + 1024))) return rc;
+    }
 }
 
 int pfsm_last_stats(pfsm_t *h, pfsm_stats *out, void *hip_stream) {

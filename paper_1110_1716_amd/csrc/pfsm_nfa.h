@@ -22,6 +22,10 @@ int nfa_add_pattern(NfaHost *h, const pfsm_nfa_desc *p, hipStream_t s);
 int nfa_remove_pattern(NfaHost *h, int32_t label, hipStream_t s);
 int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap, int64_t *d_total,
                    hipStream_t s);
+// One launch of the scan kernel: a single stream (plan == nullptr) or the
+// segments of a batch plan.
+int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
+               int64_t cap, int64_t *d_total, hipStream_t s);
 int nfa_grid_blocks(NfaHost *h);
 WorkspacePool *nfa_pool(NfaHost *h);
 

@@ -229,6 +229,25 @@ __device__ __forceinline__ void finish_launch(ScanCtl *ctl, unsigned long long *
     }
 }
 
+// Segment sg of a launch: its stream's bytes (sx, sn), the stream position
+// of its first start and its stream (-1 for a single-stream launch).
+__device__ __forceinline__ void seg_resolve(const SegPlan &p, const uint8_t *x, int64_t n, int64_t seg, int sg,
+                                            int seg_base, const uint8_t *&sx, int64_t &sn, int64_t &seg_lo,
+                                            int &stream) {
+    if (p.stream_off) {
+        stream = p.seg_stream[seg_base + sg];
+        const int64_t o0 = p.stream_off[stream], o1 = p.stream_off[stream + 1];
+        sx = x + o0;
+        sn = o1 - o0;
+        seg_lo = (int64_t)(sg - p.seg_first[stream]) * seg;
+    } else {
+        stream = -1;
+        sx = x;
+        sn = n;
+        seg_lo = (int64_t)sg * seg;
+    }
+}
+
 // The 16-byte granule of a 16-byte aligned input starting at `pos` (a
 // multiple of 16 below n).  Bytes at or past n are unspecified: callers never
 // use them.  The granule holds at least one valid byte, so it lies on a page

@@ -1,0 +1,152 @@
+"""GPU parity of the batched scan (pfsm_scan_batch) against the CPU oracle,
+stream by stream (bit-exact match lists, grouped by stream)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads.regex import regex_nfa
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1110_1716_amd as P
+    P.load_library()
+    return P
+
+
+def pack(streams):
+    """Concatenate byte streams; offsets int64 [n+1] (streams start at any byte)."""
+    off = np.zeros(len(streams) + 1, np.int64)
+    for i, s in enumerate(streams):
+        off[i + 1] = off[i] + len(s)
+    data = np.concatenate([np.frombuffer(bytes(s), np.uint8) if isinstance(s, (bytes, bytearray))
+                           else np.asarray(s, np.uint8) for s in streams]) if streams else np.zeros(0, np.uint8)
+    return data, off
+
+
+def run_batch(P, automata, streams, aut_of, out_rows=None):
+    data, off = pack(streams)
+    hs = [P.pfsm_load(a) for a in automata]
+    try:
+        d = torch.from_numpy(data.copy() if data.size else np.zeros(16, np.uint8)).cuda()
+        so = torch.from_numpy(off).cuda()
+        sa = torch.from_numpy(np.asarray(aut_of, np.int32)).cuda()
+        out = None if out_rows is None else torch.empty((out_rows, 3), dtype=torch.int32, device="cuda")
+        n, got, mo = P.pfsm_scan_batch(hs, d, so, sa, out=out)
+        return n, got.cpu().numpy(), mo.cpu().numpy()
+    finally:
+        for h in hs:
+            h.free()
+
+
+def check_batch(P, automata, streams, aut_of):
+    n, got, mo = run_batch(P, automata, streams, aut_of)
+    assert mo[0] == 0 and mo[-1] == n == len(got)
+    for i, s in enumerate(streams):
+        ref, _ = oracle.scan(automata[aut_of[i]], np.frombuffer(bytes(s), np.uint8) if isinstance(s, bytes) else s)
+        grp = got[mo[i]:mo[i + 1]]
+        assert grp.shape == ref.shape, (i, len(s), grp.shape, ref.shape)
+        assert np.array_equal(grp, ref), i
+    return n
+
+
+def mixed_automata():
+    return [W.cfg1(seed=11).automaton, W.cfg2(seed=12, n=1 << 16).automaton,
+            W.cfg3(seed=13, n=1 << 16, n_patterns=150).automaton,
+            regex_nfa([(b"a*c", 0), (b"ac", 1), (b"a(ca)*b", 2)])]
+
+
+def stream_for(rng, aut_idx, n):
+    if aut_idx in (0, 3):
+        return bytes(rng.choice(list(b"abcd"), n))
+    return rng.integers(0, 256, n, dtype=np.uint8).tobytes()
+
+
+def test_mixed_small(P):
+    rng = np.random.default_rng(1)
+    autos = mixed_automata()
+    lens = [0, 1, 2, 3, 15, 16, 17, 100, 1000, 4095, 5000, 0, 7, 33333]
+    aut_of = [int(rng.integers(0, len(autos))) for _ in lens]
+    streams = [stream_for(rng, a, n) for a, n in zip(aut_of, lens)]
+    check_batch(P, autos, streams, aut_of)
+
+
+def test_streams_longer_than_a_segment(P):
+    rng = np.random.default_rng(2)
+    wl = W.cfg2(seed=21, n=600_000)
+    nfa = W.cfg3(seed=22, n=1 << 16, n_patterns=200).automaton
+    streams = [wl.data[:200_000].tobytes(), wl.data[200_001:500_000].tobytes(),
+               rng.integers(0, 256, 150_007, dtype=np.uint8).tobytes(), wl.data[3:70_000].tobytes()]
+    check_batch(P, [wl.automaton, nfa], streams, [0, 0, 1, 1])
+
+
+def test_many_small_streams(P):
+    rng = np.random.default_rng(3)
+    autos = mixed_automata()
+    n = 700
+    aut_of = [int(a) for a in rng.integers(0, len(autos), n)]
+    lens = np.exp(rng.uniform(np.log(1), np.log(3000), n)).astype(int)
+    streams = [stream_for(rng, a, int(k)) for a, k in zip(aut_of, lens)]
+    check_batch(P, autos, streams, aut_of)
+
+
+def test_batch_equals_plain_scans(P):
+    rng = np.random.default_rng(4)
+    wl = W.cfg2(seed=41, n=1 << 18)
+    h = P.pfsm_load(wl.automaton)
+    cuts = np.sort(rng.integers(0, wl.data.size, 9))
+    streams = [wl.data[a:b].tobytes() for a, b in zip(np.r_[0, cuts], np.r_[cuts, wl.data.size])]
+    n, got, mo = run_batch(P, [wl.automaton], streams, [0] * len(streams))
+    for i, s in enumerate(streams):
+        x = torch.from_numpy(np.frombuffer(s, np.uint8).copy()).cuda() if s else torch.zeros(0, dtype=torch.uint8,
+                                                                                              device="cuda")
+        if len(s) == 0:
+            assert mo[i + 1] == mo[i]
+            continue
+        k, plain = P.pfsm_scan(h, x)
+        assert np.array_equal(got[mo[i]:mo[i + 1]], plain.cpu().numpy()), i
+    h.free()
+
+
+def test_overflow_reports_exact_count(P):
+    rng = np.random.default_rng(5)
+    autos = [W.cfg2(seed=51, n=1 << 16).automaton]
+    streams = [rng.integers(0, 256, 50_000, dtype=np.uint8).tobytes() for _ in range(3)]
+    total = sum(len(oracle.scan(autos[0], np.frombuffer(s, np.uint8))[0]) for s in streams)
+    assert total > 10
+    with pytest.raises(P.PfsmError) as ei:
+        run_batch(P, autos, streams, [0, 0, 0], out_rows=10)
+    assert ei.value.code == P.PFSM_EOVERFLOW
+    n, got, mo = run_batch(P, autos, streams, [0, 0, 0], out_rows=total)
+    assert n == total
+
+
+def test_bad_automaton_index(P):
+    autos = [W.cfg1(seed=11).automaton]
+    with pytest.raises(P.PfsmError) as ei:
+        run_batch(P, autos, [b"abcd", b"abca"], [0, 1])
+    assert ei.value.code == P.PFSM_EINVAL
+
+
+def test_empty_batch(P):
+    autos = [W.cfg1(seed=11).automaton]
+    n, got, mo = run_batch(P, autos, [], [])
+    assert n == 0 and list(mo) == [0]
+
+
+def test_repeated_batches_same_buffers(P):
+    """Back-to-back batches reuse the device workspaces (epochs, tickets)."""
+    rng = np.random.default_rng(6)
+    autos = mixed_automata()
+    for rep in range(3):
+        n = 40 + 30 * rep
+        aut_of = [int(a) for a in rng.integers(0, len(autos), n)]
+        streams = [stream_for(rng, a, int(rng.integers(0, 9000))) for a in aut_of]
+        check_batch(P, autos, streams, aut_of)
