@@ -179,11 +179,31 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
  *                       positions are relative to the stream's first byte.
  *   d_match_off         device int64 [n_streams + 1]: group offsets.
  *   n_matches           host pointer, receives the grand total.
- * PFSM_EOVERFLOW as for pfsm_scan.  Synchronises `hip_stream`.           */
+ * PFSM_EOVERFLOW: *n_matches is the exact total; d_out is unspecified.
+ * Device buffers of the batch are kept per stream and grown when a batch
+ * needs more.  Synchronises `hip_stream`.
+ * Errors: PFSM_EINVAL (arguments, an automaton index outside
+ * [0, n_automata), decreasing offsets, a stream longer than 2^31 - 16
+ * bytes, n_automata outside [1, 64]), PFSM_EOVERFLOW, PFSM_ENOMEM,
+ * PFSM_EHIP.                                                              */
 int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data,
                     const int64_t *d_stream_off, const int32_t *d_stream_automaton,
                     int32_t n_streams, pfsm_match_t *d_out, int64_t cap, int64_t *d_match_off,
                     int64_t *n_matches, void *hip_stream);
+
+/* pfsm_scan_batch without any host round trip: every step (planning, one
+ * scan launch per automaton, offsets, gather) is enqueued on `hip_stream`
+ * and nothing is allocated, so the call can be captured into a HIP graph
+ * and replayed.  The grand total is d_match_off[n_streams]; the caller
+ * compares it with cap once the stream has reached it.  The device buffers
+ * must already be large enough: run pfsm_scan_batch once on the same stream
+ * with the same or larger sizes first (PFSM_ENOMEM otherwise).  A batch
+ * whose automaton indices or offsets are invalid reports 0 matches.
+ * Errors: PFSM_EINVAL, PFSM_ENOMEM, PFSM_EHIP.                            */
+int pfsm_scan_batch_async(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data,
+                          const int64_t *d_stream_off, const int32_t *d_stream_automaton,
+                          int32_t n_streams, pfsm_match_t *d_out, int64_t cap, int64_t *d_match_off,
+                          void *hip_stream);
 
 /* Work counters of the most recent completed scan of `h` on `hip_stream`.
  * Synchronises the stream.  Errors: PFSM_EINVAL, PFSM_ENOENT (no scan yet),

@@ -10,7 +10,8 @@ missing, loading fails loudly -- there is no fallback.
 
 Names follow the C ABI: ``pfsm_load_dfa``, ``pfsm_load_nfa``,
 ``pfsm_add_pattern``, ``pfsm_remove_pattern``, ``pfsm_scan``,
-``pfsm_scan_async``, ``pfsm_scan_batch``, ``pfsm_last_stats``, ``pfsm_free``.
+``pfsm_scan_async``, ``pfsm_scan_batch``, ``pfsm_scan_batch_async``, ``pfsm_last_stats``,
+``pfsm_free``.
 """
 from __future__ import annotations
 
@@ -34,8 +35,8 @@ PFSM_ENOSYS = -7
 
 # Exported symbols of libpfsm.so, as declared in include/pfsm.h.
 EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pattern", "pfsm_scan",
-           "pfsm_scan_async", "pfsm_scan_batch", "pfsm_last_stats", "pfsm_free", "pfsm_strerror",
-           "pfsm_last_error")
+           "pfsm_scan_async", "pfsm_scan_batch", "pfsm_scan_batch_async", "pfsm_last_stats", "pfsm_free",
+           "pfsm_strerror", "pfsm_last_error")
 
 
 class PfsmError(RuntimeError):
@@ -83,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "pfsm_scan_async": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, vp]),
         "pfsm_scan_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, i32, vp, i64, vp,
                                            ctypes.POINTER(i64), vp]),
+        "pfsm_scan_batch_async": (ctypes.c_int, [vp, i32, vp, vp, vp, i32, vp, i64, vp, vp]),
         "pfsm_last_stats": (ctypes.c_int, [vp, ctypes.POINTER(_Stats), vp]),
         "pfsm_free": (None, [vp]),
         "pfsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -282,6 +284,19 @@ def pfsm_scan_batch(handles, data, stream_off, stream_automaton, out=None, match
         rc = call(out)
     _check(rc)
     return n.value, out[:n.value], match_off
+
+
+def pfsm_scan_batch_async(handles, data, stream_off, stream_automaton, out, match_off, stream=None) -> None:
+    """Enqueue a batch with no host round trip (capturable in a HIP graph);
+    the total is match_off[n_streams].  Buffers must have been sized by a
+    pfsm_scan_batch call of the same or larger size on the same stream."""
+    _check_input(data)
+    _check_out(out)
+    arr = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
+    _check(load_library().pfsm_scan_batch_async(arr, len(handles), data.data_ptr(), stream_off.data_ptr(),
+                                                stream_automaton.data_ptr(), stream_automaton.numel(),
+                                                out.data_ptr(), out.shape[0], match_off.data_ptr(),
+                                                _stream_ptr(stream)))
 
 
 def pfsm_last_stats(h: Pfsm, stream=None) -> dict:

@@ -521,10 +521,10 @@ int batch_ws(hipStream_t s, BatchWs **out) {
 
 extern "C" {
 
-int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
-                    const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
-                    int64_t *d_match_off, int64_t *n_matches, void *hip_stream) {
-    if (!hs || !n_matches || !d_match_off) return fail(PFSM_EINVAL, "NULL argument");
+static int batch_check(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
+                       const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
+                       int64_t *d_match_off) {
+    if (!hs || !d_match_off) return fail(PFSM_EINVAL, "NULL argument");
     if (n_automata < 1 || n_automata > kMaxBatchAutomata)
         return fail(PFSM_EINVAL, "n_automata must be in [1, %d]", kMaxBatchAutomata);
     for (int a = 0; a < n_automata; ++a)
@@ -534,82 +534,120 @@ int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data
         return fail(PFSM_EINVAL, "stream arrays are NULL");
     if (cap < 0) return fail(PFSM_EINVAL, "cap must be >= 0");
     if (cap > 0 && !d_out) return fail(PFSM_EINVAL, "d_out is NULL");
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    return PFSM_OK;
+}
+
+// Everything of a batch on the device: plan, one scan launch per automaton,
+// offsets and gather.  With `may_grow` the buffers are first grown to what
+// the arguments need (allocations and synchronisation); without it a buffer
+// that is too small is an error, so the work can be captured in a graph.
+static int batch_enqueue(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
+                         const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
+                         int64_t *d_match_off, hipStream_t s, bool may_grow, BatchWs **bw_out,
+                         std::vector<Workspace *> &ws, int32_t *seg_cap_out, int *lb_cap_out) {
     BatchWs *bw;
     int rc = batch_ws(s, &bw);
     if (rc) return rc;
     const int64_t ns = std::max(n_streams, 1);
-    if ((rc = grow(&bw->seg_first, &bw->c_first, ns, s))) return rc;
-    if ((rc = grow(&bw->stream_lo, &bw->c_lo, ns, s))) return rc;
-    if ((rc = grow(&bw->stream_hi, &bw->c_hi, ns, s))) return rc;
-    if ((rc = grow(&bw->n_segs, &bw->c_nsegs, n_automata, s))) return rc;
-    if ((rc = grow(&bw->seg_base, &bw->c_base, n_automata, s))) return rc;
-    if ((rc = grow(&bw->bases, &bw->c_bases, n_automata + 1, s))) return rc;
-    if ((rc = grow(&bw->stage, &bw->c_stage, std::max<int64_t>(cap, 1), s))) return rc;
-    if ((rc = grow(&bw->seg_stream, &bw->c_seg, 4 * ns + 4096, s))) return rc;
-
-    // The workspace of every automaton on this stream (look-back words, ...).
-    std::vector<Workspace *> ws(n_automata);
+    const int64_t need[8] = {ns, ns, ns, n_automata, n_automata, n_automata + 1, std::max<int64_t>(cap, 1), 4 * ns + 4096};
+    const int64_t have[8] = {bw->c_first, bw->c_lo, bw->c_hi, bw->c_nsegs, bw->c_base, bw->c_bases, bw->c_stage, bw->c_seg};
+    if (!may_grow) {
+        for (int k = 0; k < 7; ++k)
+            if (have[k] < need[k])
+                return fail(PFSM_ENOMEM, "batch buffers are smaller than this batch needs: run pfsm_scan_batch "
+                                         "with the same sizes once first");
+    } else {
+        if ((rc = grow(&bw->seg_first, &bw->c_first, need[0], s))) return rc;
+        if ((rc = grow(&bw->stream_lo, &bw->c_lo, need[1], s))) return rc;
+        if ((rc = grow(&bw->stream_hi, &bw->c_hi, need[2], s))) return rc;
+        if ((rc = grow(&bw->n_segs, &bw->c_nsegs, need[3], s))) return rc;
+        if ((rc = grow(&bw->seg_base, &bw->c_base, need[4], s))) return rc;
+        if ((rc = grow(&bw->bases, &bw->c_bases, need[5], s))) return rc;
+        if ((rc = grow(&bw->stage, &bw->c_stage, need[6], s))) return rc;
+        if ((rc = grow(&bw->seg_stream, &bw->c_seg, need[7], s))) return rc;
+    }
+    ws.assign(n_automata, nullptr);
     for (int a = 0; a < n_automata; ++a) {
         pfsm_t *h = hs[a];
         const int nb = h->kind == 1 ? nfa_grid_blocks(h->nfa.get()) : h->n_blocks;
         if ((rc = (h->kind == 1 ? nfa_pool(h->nfa.get()) : &h->pool)->get(s, nb, &ws[a]))) return rc;
     }
+    int lb_cap = 1 << 30;
+    for (Workspace *w : ws) lb_cap = std::min(lb_cap, w->lb_cap);
+    BatchPlanArgs p{};
+    p.stream_off = d_stream_off;
+    p.stream_aut = d_stream_automaton;
+    p.n_streams = n_streams;
+    p.n_aut = n_automata;
+    p.seg = kBatchSeg;
+    p.max_stream = kMaxStream;
+    p.seg_first = bw->seg_first;
+    p.seg_stream = bw->seg_stream;
+    p.n_segs = bw->n_segs;
+    p.seg_base = bw->seg_base;
+    p.bases = bw->bases;
+    p.stream_lo = bw->stream_lo;
+    p.stream_hi = bw->stream_hi;
+    p.info = bw->info;
+    p.seg_cap = (int32_t)std::min<int64_t>(bw->c_seg, 1 << 30);
+    p.lb_cap = lb_cap;
+    HIP_TRY(launch_batch_plan(p, s));
+    // One launch per automaton, each after the previous one's matches.
+    for (int a = 0; a < n_automata; ++a) {
+        SegPlan sp{};
+        sp.stream_off = d_stream_off;
+        sp.seg_stream = bw->seg_stream;
+        sp.seg_first = bw->seg_first;
+        sp.n_segs_dev = bw->n_segs + a;
+        sp.seg_base_dev = bw->seg_base + a;
+        sp.base_dev = bw->bases + a;
+        sp.stream_lo = bw->stream_lo;
+        sp.stream_hi = bw->stream_hi;
+        pfsm_t *h = hs[a];
+        rc = h->kind == 1 ? nfa_launch(h->nfa.get(), d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage,
+                                       bw->bases + a + 1, s)
+                          : dfa_launch(h, d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage, bw->bases + a + 1, s);
+        if (rc) return rc;
+    }
+    BatchGatherArgs g{};
+    g.n_streams = n_streams;
+    g.stream_lo = bw->stream_lo;
+    g.stream_hi = bw->stream_hi;
+    g.match_off = d_match_off;
+    g.stage = bw->stage;
+    g.stage_cap = bw->c_stage;
+    g.out = reinterpret_cast<MatchOut *>(d_out);
+    g.cap = cap;
+    g.info = bw->info;
+    HIP_TRY(launch_batch_gather(g, s));
+    *bw_out = bw;
+    *seg_cap_out = p.seg_cap;
+    *lb_cap_out = lb_cap;
+    return PFSM_OK;
+}
+
+int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
+                    const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
+                    int64_t *d_match_off, int64_t *n_matches, void *hip_stream) {
+    if (!n_matches) return fail(PFSM_EINVAL, "NULL argument");
+    int rc = batch_check(hs, n_automata, d_data, d_stream_off, d_stream_automaton, n_streams, d_out, cap, d_match_off);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
     for (int attempt = 0;; ++attempt) {
-        int lb_cap = 1 << 30;
-        for (Workspace *w : ws) lb_cap = std::min(lb_cap, w->lb_cap);
-        BatchPlanArgs p{};
-        p.stream_off = d_stream_off;
-        p.stream_aut = d_stream_automaton;
-        p.n_streams = n_streams;
-        p.n_aut = n_automata;
-        p.seg = kBatchSeg;
-        p.max_stream = kMaxStream;
-        p.seg_first = bw->seg_first;
-        p.seg_stream = bw->seg_stream;
-        p.n_segs = bw->n_segs;
-        p.seg_base = bw->seg_base;
-        p.bases = bw->bases;
-        p.stream_lo = bw->stream_lo;
-        p.stream_hi = bw->stream_hi;
-        p.info = bw->info;
-        p.seg_cap = (int32_t)std::min<int64_t>(bw->c_seg, 1 << 30);
-        p.lb_cap = lb_cap;
-        HIP_TRY(launch_batch_plan(p, s));
-        // One launch per automaton, each after the previous one's matches.
-        for (int a = 0; a < n_automata; ++a) {
-            SegPlan sp{};
-            sp.stream_off = d_stream_off;
-            sp.seg_stream = bw->seg_stream;
-            sp.seg_first = bw->seg_first;
-            sp.n_segs_dev = bw->n_segs + a;
-            sp.seg_base_dev = bw->seg_base + a;
-            sp.base_dev = bw->bases + a;
-            sp.stream_lo = bw->stream_lo;
-            sp.stream_hi = bw->stream_hi;
-            pfsm_t *h = hs[a];
-            rc = h->kind == 1 ? nfa_launch(h->nfa.get(), d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage,
-                                           bw->bases + a + 1, s)
-                              : dfa_launch(h, d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage, bw->bases + a + 1, s);
-            if (rc) return rc;
-        }
-        BatchGatherArgs g{};
-        g.n_streams = n_streams;
-        g.stream_lo = bw->stream_lo;
-        g.stream_hi = bw->stream_hi;
-        g.match_off = d_match_off;
-        g.stage = bw->stage;
-        g.stage_cap = bw->c_stage;
-        g.out = reinterpret_cast<MatchOut *>(d_out);
-        g.cap = cap;
-        g.info = bw->info;
-        HIP_TRY(launch_batch_gather(g, s));
+        BatchWs *bw;
+        std::vector<Workspace *> ws;
+        int32_t seg_cap;
+        int lb_cap;
+        if ((rc = batch_enqueue(hs, n_automata, d_data, d_stream_off, d_stream_automaton, n_streams, d_out, cap,
+                                d_match_off, s, true, &bw, ws, &seg_cap, &lb_cap)))
+            return rc;
         HIP_TRY(hipMemcpyAsync(bw->h_info, bw->info, sizeof(BatchInfo), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const BatchInfo info = *bw->h_info;
         if (info.err == 1) return fail(PFSM_EINVAL, "a stream names an automaton outside [0, %d)", n_automata);
-        if (info.err) return fail(PFSM_EINVAL, "stream offsets must not decrease and streams must be at most 2^31 - 16 bytes");
-        const bool more_segs = info.total_segs > p.seg_cap, more_lb = info.max_segs > lb_cap;
+        if (info.err)
+            return fail(PFSM_EINVAL, "stream offsets must not decrease and streams must be at most 2^31 - 16 bytes");
+        const bool more_segs = info.total_segs > seg_cap, more_lb = info.max_segs > lb_cap;
         if (!more_segs && !more_lb) {
             *n_matches = info.total;
             if (info.total > cap)
@@ -622,6 +660,19 @@ int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data
             for (Workspace *w : ws)
                 if ((rc = grow_lb(w, info.max_segs + 1024))) return rc;
     }
+}
+
+int pfsm_scan_batch_async(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
+                          const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
+                          int64_t *d_match_off, void *hip_stream) {
+    int rc = batch_check(hs, n_automata, d_data, d_stream_off, d_stream_automaton, n_streams, d_out, cap, d_match_off);
+    if (rc) return rc;
+    BatchWs *bw;
+    std::vector<Workspace *> ws;
+    int32_t seg_cap;
+    int lb_cap;
+    return batch_enqueue(hs, n_automata, d_data, d_stream_off, d_stream_automaton, n_streams, d_out, cap, d_match_off,
+                         static_cast<hipStream_t>(hip_stream), false, &bw, ws, &seg_cap, &lb_cap);
 }
 
 int pfsm_last_stats(pfsm_t *h, pfsm_stats *out, void *hip_stream) {

@@ -150,3 +150,97 @@ def test_repeated_batches_same_buffers(P):
         aut_of = [int(a) for a in rng.integers(0, len(autos), n)]
         streams = [stream_for(rng, a, int(rng.integers(0, 9000))) for a in aut_of]
         check_batch(P, autos, streams, aut_of)
+
+
+def _cfg4_refs(wl, removed, added):
+    """Oracle lists per stream for cfg4 after NFA edits: the union of the
+    base NFA and every added pattern, without the removed labels."""
+    from oracle import compose
+    nfa_i = wl.meta["nfa_index"]
+    nfa = compose.union([wl.automata[nfa_i]] + added) if added else wl.automata[nfa_i]
+    refs = []
+    for s in range(len(wl.stream_automaton)):
+        x = wl.data[wl.stream_off[s]:wl.stream_off[s + 1]]
+        a = int(wl.stream_automaton[s])
+        ref, _ = oracle.scan(nfa if a == nfa_i else wl.automata[a], x)
+        if a == nfa_i:
+            for lab in removed:
+                ref = compose.drop_label(ref, lab)
+        refs.append(ref)
+    return refs
+
+
+def _batch_lists(P, hs, wl):
+    d = torch.from_numpy(wl.data.copy()).cuda()
+    so = torch.from_numpy(wl.stream_off).cuda()
+    sa = torch.from_numpy(wl.stream_automaton).cuda()
+    n, got, mo = P.pfsm_scan_batch(hs, d, so, sa)
+    got, mo = got.cpu().numpy(), mo.cpu().numpy()
+    return [got[mo[s]:mo[s + 1]] for s in range(len(wl.stream_automaton))]
+
+
+def test_cfg4_small_with_edits(P):
+    """The batched workload (four DFAs of 256-4,096 states and an NFA union)
+    at a small size, before and after add/remove edits of the NFA."""
+    wl = W.cfg4(seed=44, n_streams=80, len_hi=1 << 15, n_patterns=150, n_ops=8)
+    hs = [P.pfsm_load(a) for a in wl.automata]
+    try:
+        refs = _cfg4_refs(wl, [], [])
+        for s, grp in enumerate(_batch_lists(P, hs, wl)):
+            assert np.array_equal(grp, refs[s]), s
+        nfa_h = hs[wl.meta["nfa_index"]]
+        removed, added = [], []
+        for op in wl.ops:
+            if op[0] == "add":
+                P.pfsm_add_pattern(nfa_h, op[1])
+                added.append(op[1])
+            else:
+                P.pfsm_remove_pattern(nfa_h, op[1])
+                removed.append(op[1])
+        refs = _cfg4_refs(wl, removed, added)
+        for s, grp in enumerate(_batch_lists(P, hs, wl)):
+            assert np.array_equal(grp, refs[s]), s
+    finally:
+        for h in hs:
+            h.free()
+
+
+def test_graph_capture_replays(P):
+    """pfsm_scan_batch_async captured in a HIP graph: every replay, with eager
+    scans in between, equals the eager batch."""
+    wl = W.cfg4(seed=45, n_streams=60, len_hi=1 << 15, n_patterns=100, n_ops=0)
+    hs = [P.pfsm_load(a) for a in wl.automata]
+    try:
+        s = torch.cuda.Stream()
+        d = torch.from_numpy(wl.data.copy()).cuda()
+        so = torch.from_numpy(wl.stream_off).cuda()
+        sa = torch.from_numpy(wl.stream_automaton).cuda()
+        cap = wl.data.size // 16 + 1024
+        with torch.cuda.stream(s):
+            out_e = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+            n_e, got_e, mo_e = P.pfsm_scan_batch(hs, d, so, sa, out=out_e, stream=s)
+            got_e, mo_e = got_e.cpu().numpy().copy(), mo_e.cpu().numpy().copy()
+            out_g = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+            mo_g = torch.empty(len(wl.stream_automaton) + 1, dtype=torch.int64, device="cuda")
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            P.pfsm_scan_batch_async(hs, d, so, sa, out_g, mo_g, stream=s)
+        other = W.cfg2(seed=46, n=1 << 17)
+        h2 = P.pfsm_load(other.automaton)
+        x2 = torch.from_numpy(other.data.copy()).cuda()
+        for rep in range(3):
+            out_g.fill_(-1)
+            mo_g.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(mo_g.cpu().numpy(), mo_e), rep
+            assert np.array_equal(out_g[:n_e].cpu().numpy(), got_e), rep
+            P.pfsm_scan(h2, x2)  # eager work between replays
+            P.pfsm_scan_batch(hs, d, so, sa, stream=s)
+            torch.cuda.synchronize()
+        h2.free()
+    finally:
+        for h in hs:
+            h.free()

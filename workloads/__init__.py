@@ -453,3 +453,81 @@ def cfg3(seed: int = 3, n: int = 64 * MiB, n_patterns: int = 2000, plant_rate: f
             plants.append((off, w.size, sig.label))
     return Workload(f"NFA union of {n_patterns} signature chains, {n >> 20} MiB Zipf(1.1) bytes",
                     nfa, x, seed, {"plants": plants, "signatures": sigs, "perm": perm})
+
+
+@dataclass
+class BatchWorkload:
+    name: str
+    automata: list  # DFAs and NFAs, indexed by stream_automaton
+    data: np.ndarray  # every stream, concatenated (uint8)
+    stream_off: np.ndarray  # int64 [n_streams + 1]
+    stream_automaton: np.ndarray  # int32 [n_streams]
+    seed: int
+    ops: list = field(default_factory=list)  # edits of the NFA between batches
+    meta: dict = field(default_factory=dict)
+
+
+def _plant_pool_dfa(rng: np.random.Generator, d: DFA, k: int) -> List[np.ndarray]:
+    tbl = d.delta.reshape(d.n_states, d.n_symbols)
+    live = [np.nonzero(tbl[q] >= 0)[0] for q in range(d.n_states)]
+    return [_plant_walk(rng, d, live, np.arange(256)) for _ in range(k)]
+
+
+def cfg4(seed: int = 4, n_streams: int = 4096, len_lo: int = 64, len_hi: int = MiB,
+         dfa_states: Sequence[int] = (256, 1024, 2048, 4096), n_patterns: int = 2000, n_ops: int = 100,
+         plant_every: int = 4 * KiB, plant_rate: float = 1e-4, pool: int = 256) -> BatchWorkload:
+    """Batched scan: four random byte DFAs of 256-4,096 states (cfg2 recipe:
+    dead entries p=0.9, 16 finals) and one NFA union of signature chains (cfg3
+    recipe); n_streams streams with lengths log-uniform on [len_lo, len_hi],
+    each assigned a uniformly drawn automaton.  DFA streams hold uniform bytes
+    with one accepting walk planted per 4 KiB; NFA streams hold Zipf(1.1)
+    bytes with signature instances planted at plant_rate per byte.  Planted
+    strings are drawn from a seeded pool of `pool` per automaton.  ``ops``
+    lists n_ops edits of the NFA, alternately adding a fresh chain with a new
+    label and removing a uniformly drawn present label."""
+    rng = rng_for(seed)
+    dfas = [random_table_dfa(rng, int(n), 256, 0.9, 16) for n in dfa_states]
+    sigs = signature_union(rng, n_patterns)
+    nfa = union_nfa(sigs)
+    perm = rng.permutation(256).astype(np.uint8)
+    automata = list(dfas) + [nfa]
+    nfa_idx = len(dfas)
+    lens = np.exp(rng.uniform(np.log(len_lo), np.log(len_hi), n_streams)).astype(np.int64)
+    aut = rng.integers(0, len(automata), n_streams).astype(np.int32)
+    off = np.zeros(n_streams + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    data = rng.integers(0, 256, int(off[-1]), dtype=np.uint8)
+    pools = [_plant_pool_dfa(rng, d, pool) for d in dfas]
+    inst = [_instance_bytes(rng, sigs[int(rng.integers(0, len(sigs)))], 64, perm) for _ in range(pool)]
+    for s in range(n_streams):
+        lo, hi = int(off[s]), int(off[s + 1])
+        n = hi - lo
+        if aut[s] == nfa_idx:
+            data[lo:hi] = zipf_bytes(rng, n, perm=perm)
+            for _ in range(int(rng.binomial(n, plant_rate))):
+                w = inst[int(rng.integers(0, pool))]
+                if w.size <= n:
+                    at = lo + int(rng.integers(0, n - w.size + 1))
+                    data[at:at + w.size] = w
+        else:
+            pl = pools[int(aut[s])]
+            for blk in range(n // plant_every):
+                w = pl[int(rng.integers(0, pool))]
+                at = lo + blk * plant_every + int(rng.integers(0, plant_every - w.size + 1))
+                data[at:at + w.size] = w
+    ops = []
+    present = [s.label for s in sigs]
+    nxt = n_patterns
+    for i in range(n_ops):
+        if i % 2 == 0:
+            sig = signature_union(rng, 1, label_base=nxt)
+            ops.append(("add", union_nfa(sig), [nxt]))
+            present.append(nxt)
+            nxt += 1
+        else:
+            lab = present.pop(int(rng.integers(0, len(present))))
+            ops.append(("remove", lab))
+    return BatchWorkload(f"{n_streams} streams log-uniform {len_lo} B-{len_hi >> 10} KiB over 4 random DFAs "
+                         f"({'/'.join(str(int(n)) for n in dfa_states)} states) and an NFA union of "
+                         f"{n_patterns} signatures", automata, data, off, aut, seed, ops,
+                         {"nfa_index": nfa_idx, "signatures": sigs, "perm": perm})
