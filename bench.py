@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--batch-replays", type=int, default=10)
     return ap.parse_args()
 
 
@@ -69,6 +71,84 @@ def measured_traffic():
     if fields.get("kernel_source_sha256") != h.hexdigest():
         return None
     return int(fields["traffic_bytes_per_launch"])
+
+
+def batched_vs_plain(replays: int):
+    """The batched workload: 4,096 streams (64 B-1 MiB, log-uniform) over four
+    random byte DFAs (256-4,096 states) and an NFA union of 2,000 signatures.
+    Batched = one HIP-graph replay of pfsm_scan_batch_async per batch;
+    plain = one synchronous pfsm_scan per stream.  Between the two halves of
+    the batched runs the workload's 100 NFA edits are applied (and timed)."""
+    import torch
+    import workloads as W
+    import paper_1110_1716_amd as P
+    wl = W.cfg4()
+    hs = [P.pfsm_load(a) for a in wl.automata]
+    d = torch.from_numpy(wl.data).cuda()
+    so = torch.from_numpy(wl.stream_off).cuda()
+    sa = torch.from_numpy(wl.stream_automaton).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        n0, got, mo = P.pfsm_scan_batch(hs, d, so, sa, stream=s)
+        cap = int(n0) * 2 + 4096
+        out = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+        mo_g = torch.empty_like(mo)
+    s.synchronize()
+
+    def graph_runs(k):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            P.pfsm_scan_batch_async(hs, d, so, sa, out, mo_g, stream=s)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s):
+            e0.record(s)
+            for _ in range(k):
+                g.replay()
+            e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k, int(mo_g[-1].item())
+
+    ms1, n1 = graph_runs(replays)
+    if n1 != n0:
+        raise SystemExit(f"batched replay count {n1} != {n0}")
+    nfa_h = hs[wl.meta["nfa_index"]]
+    lat = []
+    for op in wl.ops:
+        t0 = time.perf_counter()
+        if op[0] == "add":
+            P.pfsm_add_pattern(nfa_h, op[1])
+        else:
+            P.pfsm_remove_pattern(nfa_h, op[1])
+        lat.append((time.perf_counter() - t0) * 1e3)
+    with torch.cuda.stream(s):
+        n2, _, _ = P.pfsm_scan_batch(hs, d, so, sa, stream=s)
+    ms2, _ = graph_runs(replays)
+    # plain: one synchronous scan per stream, same bytes, after the edits
+    outp = torch.empty((1 << 20, 3), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = 0
+    for i in range(len(wl.stream_automaton)):
+        lo, hi = int(wl.stream_off[i]), int(wl.stream_off[i + 1])
+        tot += P.pfsm_scan(hs[int(wl.stream_automaton[i])], d[lo:hi], out=outp)[0]
+    plain_s = time.perf_counter() - t0
+    if tot != n2:
+        raise SystemExit(f"plain total {tot} != batched {n2}")
+    for h in hs:
+        h.free()
+    ms = (ms1 + ms2) / 2
+    gbs = wl.data.size / (ms / 1e3) / 1e9
+    plain = wl.data.size / plain_s / 1e9
+    return {"workload": wl.name, "n_streams": int(len(wl.stream_automaton)), "bytes": int(wl.data.size),
+            "matches_before_edits": int(n0), "matches_after_edits": int(n2),
+            "batched_gbs": round(gbs, 2), "batched_ms": round(ms, 3),
+            "batched_ms_before_after_edits": [round(ms1, 3), round(ms2, 3)],
+            "plain_gbs": round(plain, 3), "plain_ms": round(plain_s * 1e3, 1),
+            "speedup": round(gbs / plain, 2), "launch": "one HIP graph replay per batch",
+            "edits": {"ops": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 2)}}
 
 
 def cpu_baseline(wl, seconds: float):
@@ -195,9 +275,11 @@ def main():
                      "alg_bytes_per_launch": int(alg_bytes)},
         "wall_s_timed": round(wall, 4),
     }
+    h.free()
+    if not args.no_batch:
+        res["batched"] = batched_vs_plain(args.batch_replays)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    h.free()
     print(json.dumps(res), flush=True)
 
 

@@ -205,6 +205,44 @@ int pfsm_scan_batch_async(pfsm_t *const *hs, int32_t n_automata, const uint8_t *
                           int32_t n_streams, pfsm_match_t *d_out, int64_t cap, int64_t *d_match_off,
                           void *hip_stream);
 
+/* ---------------------------------------------------------------------
+ * Serving loop: continuous batching of scan requests (the online use of
+ * Section I) against resident handles.  A worker thread admits queued
+ * requests, first come first served, into one of two batches while their
+ * bytes plus an output estimate (n/16 + 256 matches each, charged twice for
+ * the device and host copies) fit `mem_budget` bytes, and runs each batch
+ * as pfsm_scan_batch does on a stream of its own; a request arriving while
+ * batches run joins the next one as soon as a batch slot and memory free up.
+ * A request larger than the budget runs alone.  Each request's matches are
+ * exactly those of pfsm_scan on its bytes alone.
+ * --------------------------------------------------------------------- */
+typedef struct pfsm_server pfsm_server_t;
+
+typedef struct {
+    int64_t batches, reruns, requests, bytes, matches, peak_inflight;
+} pfsm_server_stats;
+
+/* Start a server over n_automata handles (1..64), which must outlive it and
+ * must not be edited while it runs.  The device is the current one.
+ * Errors: PFSM_EINVAL, PFSM_ENOMEM, PFSM_EHIP.                            */
+int pfsm_server_create(pfsm_server_t **out, pfsm_t *const *hs, int32_t n_automata, int64_t mem_budget,
+                       int32_t max_batch);
+/* Queue a scan of n host bytes (copied during the call) against handle
+ * `automaton`; *id names the request.  Errors: PFSM_EINVAL.               */
+int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n, int64_t *id);
+/* Block until request `id` is done; *matches (host memory owned by the
+ * server until pfsm_server_release) holds its *n_matches matches in
+ * ascending (start, end, label) order.  Errors: PFSM_ENOENT, or the error
+ * the request's batch met.                                                */
+int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches, int64_t *n_matches);
+/* Forget a finished request and its matches.  Errors: PFSM_ENOENT,
+ * PFSM_EINVAL (not finished).                                             */
+int pfsm_server_release(pfsm_server_t *sv, int64_t id);
+/* Counters since creation.                                                */
+int pfsm_server_stats_get(pfsm_server_t *sv, pfsm_server_stats *out);
+/* Finish every queued request, stop the worker and free the server.       */
+void pfsm_server_destroy(pfsm_server_t *sv);
+
 /* Work counters of the most recent completed scan of `h` on `hip_stream`.
  * Synchronises the stream.  Errors: PFSM_EINVAL, PFSM_ENOENT (no scan yet),
  * PFSM_EHIP.                                                              */

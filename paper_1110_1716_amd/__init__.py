@@ -36,7 +36,8 @@ PFSM_ENOSYS = -7
 # Exported symbols of libpfsm.so, as declared in include/pfsm.h.
 EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pattern", "pfsm_scan",
            "pfsm_scan_async", "pfsm_scan_batch", "pfsm_scan_batch_async", "pfsm_last_stats", "pfsm_free",
-           "pfsm_strerror", "pfsm_last_error")
+           "pfsm_strerror", "pfsm_last_error", "pfsm_server_create", "pfsm_server_submit", "pfsm_server_wait",
+           "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy")
 
 
 class PfsmError(RuntimeError):
@@ -61,6 +62,11 @@ class _NfaDesc(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("transitions", ctypes.c_int64), ("activations", ctypes.c_int64),
                 ("matches", ctypes.c_int64), ("long_walks", ctypes.c_int64)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("reruns", ctypes.c_int64), ("requests", ctypes.c_int64),
+                ("bytes", ctypes.c_int64), ("matches", ctypes.c_int64), ("peak_inflight", ctypes.c_int64)]
 
 
 _lib = None
@@ -88,6 +94,12 @@ def load_library(path: str = LIB_PATH):
         "pfsm_last_stats": (ctypes.c_int, [vp, ctypes.POINTER(_Stats), vp]),
         "pfsm_free": (None, [vp]),
         "pfsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "pfsm_server_create": (ctypes.c_int, [ctypes.POINTER(vp), vp, i32, i64, i32]),
+        "pfsm_server_submit": (ctypes.c_int, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+        "pfsm_server_wait": (ctypes.c_int, [vp, i64, ctypes.POINTER(vp), ctypes.POINTER(i64)]),
+        "pfsm_server_release": (ctypes.c_int, [vp, i64]),
+        "pfsm_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(_ServerStats)]),
+        "pfsm_server_destroy": (None, [vp]),
         "pfsm_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -308,3 +320,58 @@ def pfsm_last_stats(h: Pfsm, stream=None) -> dict:
 
 def pfsm_free(h: Pfsm) -> None:
     h.free()
+
+
+class Server:
+    """Continuous-batching scan server over resident handles (include/pfsm.h,
+    pfsm_server_*).  Requests are host byte strings; results are
+    int32 [k, 3] arrays of (start, end, label), ascending."""
+
+    def __init__(self, handles, mem_budget: int = 1 << 30, max_batch: int = 4096):
+        lib = load_library()
+        self._handles = list(handles)
+        arr = (ctypes.c_void_p * len(self._handles))(*[h.ptr for h in self._handles])
+        p = ctypes.c_void_p()
+        _check(lib.pfsm_server_create(ctypes.byref(p), arr, len(self._handles), int(mem_budget), int(max_batch)))
+        self._ptr = p.value
+
+    def submit(self, automaton: int, data) -> int:
+        a = np.ascontiguousarray(np.frombuffer(data, np.uint8) if isinstance(data, (bytes, bytearray))
+                                 else np.asarray(data, np.uint8))
+        rid = ctypes.c_int64()
+        _check(load_library().pfsm_server_submit(self._ptr, int(automaton), a.ctypes.data if a.size else None,
+                                                 a.size, ctypes.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int, release: bool = True) -> np.ndarray:
+        lib = load_library()
+        ptr, n = ctypes.c_void_p(), ctypes.c_int64()
+        _check(lib.pfsm_server_wait(self._ptr, int(rid), ctypes.byref(ptr), ctypes.byref(n)))
+        k = n.value
+        out = (np.frombuffer((ctypes.c_int32 * (3 * k)).from_address(ptr.value), np.int32).reshape(k, 3).copy()
+               if k else np.zeros((0, 3), np.int32))
+        if release:
+            _check(lib.pfsm_server_release(self._ptr, int(rid)))
+        return out
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(load_library().pfsm_server_stats_get(self._ptr, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            load_library().pfsm_server_destroy(self._ptr)
+            self._ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

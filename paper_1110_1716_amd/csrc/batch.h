@@ -5,9 +5,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "pfsm_dev.h"
 
+struct pfsm;
+
 namespace pfsmk {
+
+struct Workspace;
 
 constexpr int kMaxBatchAutomata = 64;
 constexpr int64_t kBatchSeg = 65536;  // bytes per segment (both scan kernels)
@@ -49,5 +55,24 @@ struct BatchGatherArgs {
 
 hipError_t launch_batch_plan(const BatchPlanArgs &p, hipStream_t s);
 hipError_t launch_batch_gather(const BatchGatherArgs &g, hipStream_t s);
+
+// A batch enqueued by batch_run: what the device reports about it is in
+// *info (device memory) once the stream has reached the batch's end.
+struct BatchRun {
+    BatchInfo *info = nullptr;
+    int32_t seg_cap = 0;
+    int lb_cap = 0;
+    std::vector<struct Workspace *> ws;
+    void *bw = nullptr;
+};
+
+// Enqueue a whole batch on s (buffers grown first, which may synchronise s).
+int batch_run(struct ::pfsm *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
+              const int32_t *d_stream_automaton, int32_t n_streams, MatchOut *d_out, int64_t cap,
+              int64_t *d_match_off, hipStream_t s, BatchRun *run);
+// After a batch whose plan did not fit (info.total_segs > seg_cap or
+// info.max_segs > lb_cap): grow what it needs.  Returns true in *again when
+// the batch must be enqueued again.
+int batch_fit(BatchRun *run, const BatchInfo &info, hipStream_t s, bool *again);
 
 }  // namespace pfsmk

@@ -626,6 +626,47 @@ static int batch_enqueue(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d
     return PFSM_OK;
 }
 
+}  // extern "C"
+
+namespace pfsmk {
+
+int batch_run(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
+              const int32_t *d_stream_automaton, int32_t n_streams, MatchOut *d_out, int64_t cap,
+              int64_t *d_match_off, hipStream_t s, BatchRun *run) {
+    int rc = batch_check(hs, n_automata, d_data, d_stream_off, d_stream_automaton, n_streams,
+                         reinterpret_cast<pfsm_match_t *>(d_out), cap, d_match_off);
+    if (rc) return rc;
+    BatchWs *bw;
+    rc = batch_enqueue(hs, n_automata, d_data, d_stream_off, d_stream_automaton, n_streams,
+                       reinterpret_cast<pfsm_match_t *>(d_out), cap, d_match_off, s, true, &bw, run->ws,
+                       &run->seg_cap, &run->lb_cap);
+    if (rc) return rc;
+    run->bw = bw;
+    run->info = bw->info;
+    return PFSM_OK;
+}
+
+int batch_fit(BatchRun *run, const BatchInfo &info, hipStream_t s, bool *again) {
+    *again = false;
+    if (info.err) return fail(PFSM_EINVAL, "invalid stream table");
+    BatchWs *bw = static_cast<BatchWs *>(run->bw);
+    int rc;
+    if (info.total_segs > run->seg_cap) {
+        if ((rc = grow(&bw->seg_stream, &bw->c_seg, (int64_t)info.total_segs + 4096, s))) return rc;
+        *again = true;
+    }
+    if (info.max_segs > run->lb_cap) {
+        for (Workspace *w : run->ws)
+            if ((rc = grow_lb(w, info.max_segs + 1024))) return rc;
+        *again = true;
+    }
+    return PFSM_OK;
+}
+
+}  // namespace pfsmk
+
+extern "C" {
+
 int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, const int64_t *d_stream_off,
                     const int32_t *d_stream_automaton, int32_t n_streams, pfsm_match_t *d_out, int64_t cap,
                     int64_t *d_match_off, int64_t *n_matches, void *hip_stream) {

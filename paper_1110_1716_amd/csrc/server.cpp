@@ -1,0 +1,355 @@
+// Serving loop: continuous batching of scan requests against resident
+// automata (the online use of Section I: matches are reported for streams as
+// they come in).
+//
+// One worker thread owns the device side.  Requests wait in a FIFO; the
+// worker packs as many as fit the memory budget (their bytes plus an output
+// estimate) into a free slot and enqueues the whole batch on that slot's
+// stream (planning, one scan launch per automaton, offsets, gather; see
+// batch.hip), then goes on admitting into the other slot while the first
+// batch runs.  When a slot's batch is done its matches are copied back and
+// handed to the waiting callers.  A batch whose output outgrows the
+// estimate is run again at the exact size (the total is known by then).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "batch.h"
+#include "host_common.h"
+#include "pfsm.h"
+
+using namespace pfsmk;
+
+namespace {
+
+constexpr int kSlots = 2;
+
+struct Req {
+    int64_t id = 0;
+    int32_t aut = 0;
+    std::vector<uint8_t> bytes;
+    std::vector<pfsm_match_t> result;
+    int status = PFSM_OK;
+    bool done = false;
+};
+
+// A buffer that only grows (contents are not kept).
+struct Buf {
+    void *p = nullptr;
+    int64_t cap = 0;
+    bool pinned = false;
+    int reserve(int64_t need) {
+        if (need <= cap) return PFSM_OK;
+        release();
+        const int64_t n = std::max<int64_t>(need, 256);
+        if (pinned) HIP_TRY(hipHostMalloc(&p, (size_t)n, hipHostMallocDefault));
+        else HIP_TRY(hipMalloc(&p, (size_t)n));
+        cap = n;
+        return PFSM_OK;
+    }
+    void release() {
+        if (p) (void)(pinned ? hipHostFree(p) : hipFree(p));
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T *as() const {
+        return static_cast<T *>(p);
+    }
+};
+
+// Host and device buffers of one batch in flight.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    std::vector<Req *> reqs;
+    int64_t bytes = 0;    // input bytes of this batch
+    int64_t out_cap = 0;  // output rows reserved for it
+    Buf h_data{nullptr, 0, true}, h_off{nullptr, 0, true}, h_aut{nullptr, 0, true}, h_moff{nullptr, 0, true},
+        h_out{nullptr, 0, true}, h_info{nullptr, 0, true};
+    Buf d_data, d_off, d_aut, d_moff, d_out;
+    BatchRun run;
+
+    void release() {
+        for (Buf *b : {&h_data, &h_off, &h_aut, &h_moff, &h_out, &h_info, &d_data, &d_off, &d_aut, &d_moff, &d_out})
+            b->release();
+        if (ev) (void)hipEventDestroy(ev);
+        if (stream) (void)hipStreamDestroy(stream);
+        ev = nullptr;
+        stream = nullptr;
+    }
+};
+
+}  // namespace
+
+struct pfsm_server {
+    std::vector<pfsm_t *> hs;
+    int device = 0;
+    int64_t budget = 0;
+    int32_t max_batch = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req *> queue;
+    std::unordered_map<int64_t, std::unique_ptr<Req>> reqs;
+    int64_t next_id = 1;
+    bool stop = false;
+    Slot slots[kSlots];
+    std::thread worker;
+    int64_t inflight = 0;  // bytes charged to busy slots (worker thread only)
+    pfsm_server_stats st{};
+
+    static int64_t out_estimate(int64_t n) { return n / 16 + 256; }
+    static int64_t charge(int64_t bytes, int64_t out_rows) {
+        return bytes + out_rows * (int64_t)(sizeof(pfsm_match_t) * 2);
+    }
+
+    void finish(Slot &sl, int status) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (Req *r : sl.reqs) {
+                if (status != PFSM_OK) r->status = status;
+                r->done = true;
+            }
+            st.requests += (int64_t)sl.reqs.size();
+            st.bytes += sl.bytes;
+        }
+        cv_done.notify_all();
+        inflight -= charge(sl.bytes, sl.out_cap);
+        sl.reqs.clear();
+        sl.busy = false;
+    }
+
+    // Copy the slot's requests into its buffers and enqueue the batch.
+    int launch(Slot &sl) {
+        const int64_t nr = (int64_t)sl.reqs.size();
+        int rc;
+        if ((rc = sl.h_data.reserve(sl.bytes))) return rc;
+        if ((rc = sl.d_data.reserve(sl.bytes + 16))) return rc;
+        if ((rc = sl.h_off.reserve(8 * (nr + 1)))) return rc;
+        if ((rc = sl.d_off.reserve(8 * (nr + 1)))) return rc;
+        if ((rc = sl.h_moff.reserve(8 * (nr + 1)))) return rc;
+        if ((rc = sl.d_moff.reserve(8 * (nr + 1)))) return rc;
+        if ((rc = sl.h_aut.reserve(4 * nr))) return rc;
+        if ((rc = sl.d_aut.reserve(4 * nr))) return rc;
+        if ((rc = sl.d_out.reserve(sl.out_cap * (int64_t)sizeof(MatchOut)))) return rc;
+        if ((rc = sl.h_info.reserve(sizeof(BatchInfo)))) return rc;
+        int64_t pos = 0;
+        for (int64_t j = 0; j < nr; ++j) {
+            Req *r = sl.reqs[j];
+            sl.h_off.as<int64_t>()[j] = pos;
+            sl.h_aut.as<int32_t>()[j] = r->aut;
+            if (!r->bytes.empty()) std::memcpy(sl.h_data.as<uint8_t>() + pos, r->bytes.data(), r->bytes.size());
+            pos += (int64_t)r->bytes.size();
+        }
+        sl.h_off.as<int64_t>()[nr] = pos;
+        if (pos) HIP_TRY(hipMemcpyAsync(sl.d_data.p, sl.h_data.p, pos, hipMemcpyHostToDevice, sl.stream));
+        HIP_TRY(hipMemcpyAsync(sl.d_off.p, sl.h_off.p, 8 * (nr + 1), hipMemcpyHostToDevice, sl.stream));
+        HIP_TRY(hipMemcpyAsync(sl.d_aut.p, sl.h_aut.p, 4 * nr, hipMemcpyHostToDevice, sl.stream));
+        if ((rc = batch_run(hs.data(), (int32_t)hs.size(), sl.d_data.as<uint8_t>(), sl.d_off.as<int64_t>(),
+                            sl.d_aut.as<int32_t>(), (int32_t)nr, sl.d_out.as<MatchOut>(), sl.out_cap,
+                            sl.d_moff.as<int64_t>(), sl.stream, &sl.run)))
+            return rc;
+        HIP_TRY(hipMemcpyAsync(sl.h_moff.p, sl.d_moff.p, 8 * (nr + 1), hipMemcpyDeviceToHost, sl.stream));
+        HIP_TRY(hipMemcpyAsync(sl.h_info.p, sl.run.info, sizeof(BatchInfo), hipMemcpyDeviceToHost, sl.stream));
+        HIP_TRY(hipEventRecord(sl.ev, sl.stream));
+        std::lock_guard<std::mutex> lk(mu);
+        ++st.batches;
+        return PFSM_OK;
+    }
+
+    // The slot's batch has finished: deliver its results, or run it again.
+    int complete(Slot &sl) {
+        const int64_t nr = (int64_t)sl.reqs.size();
+        const BatchInfo info = *sl.h_info.as<BatchInfo>();
+        bool again = false;
+        int rc = batch_fit(&sl.run, info, sl.stream, &again);
+        if (rc) return rc;
+        const int64_t *mo = sl.h_moff.as<int64_t>();
+        const int64_t total = mo[nr];
+        if (!again && total > sl.out_cap) {
+            inflight += charge(0, total - sl.out_cap);
+            sl.out_cap = total;
+            again = true;
+        }
+        if (again) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                ++st.reruns;
+            }
+            return launch(sl);
+        }
+        if ((rc = sl.h_out.reserve(std::max<int64_t>(total, 1) * (int64_t)sizeof(pfsm_match_t)))) return rc;
+        if (total) {
+            HIP_TRY(hipMemcpyAsync(sl.h_out.p, sl.d_out.p, total * sizeof(pfsm_match_t), hipMemcpyDeviceToHost,
+                                   sl.stream));
+            HIP_TRY(hipStreamSynchronize(sl.stream));
+        }
+        const pfsm_match_t *m = sl.h_out.as<pfsm_match_t>();
+        for (int64_t j = 0; j < nr; ++j) sl.reqs[j]->result.assign(m + mo[j], m + mo[j + 1]);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            st.matches += total;
+        }
+        finish(sl, PFSM_OK);
+        return PFSM_OK;
+    }
+
+    // Take queued requests for a batch (FIFO) while they fit the budget.
+    bool admit(Slot &sl) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (queue.empty()) return false;
+        int64_t bytes = 0, rows = 0;
+        while (!queue.empty() && (int32_t)sl.reqs.size() < max_batch) {
+            Req *r = queue.front();
+            const int64_t n = (int64_t)r->bytes.size();
+            const int64_t add = charge(bytes + n, rows + out_estimate(n)) - charge(bytes, rows);
+            // the first request of a batch is admitted when nothing else is in
+            // flight, so a request larger than the budget still runs
+            const bool first_alone = sl.reqs.empty() && inflight == 0;
+            if (!first_alone && inflight + charge(bytes, rows) + add > budget) break;
+            queue.pop_front();
+            sl.reqs.push_back(r);
+            bytes += n;
+            rows += out_estimate(n);
+        }
+        if (sl.reqs.empty()) return false;
+        sl.bytes = bytes;
+        sl.out_cap = rows;
+        inflight += charge(bytes, rows);
+        st.peak_inflight = std::max(st.peak_inflight, inflight);
+        return true;
+    }
+
+    void loop() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            bool progress = false;
+            for (Slot &sl : slots) {
+                if (!sl.busy || hipEventQuery(sl.ev) != hipSuccess) continue;
+                const int rc = complete(sl);
+                if (rc) finish(sl, rc);
+                progress = true;
+            }
+            for (Slot &sl : slots) {
+                if (sl.busy) continue;
+                if (!admit(sl)) break;
+                sl.busy = true;
+                const int rc = launch(sl);
+                if (rc) finish(sl, rc);
+                progress = true;
+            }
+            if (progress) continue;
+            bool any_busy = false;
+            for (Slot &sl : slots) any_busy |= sl.busy;
+            std::unique_lock<std::mutex> lk(mu);
+            if (stop && queue.empty() && !any_busy) return;
+            if (any_busy) {
+                // a batch is on the device: poll it, waking early for new work
+                cv_work.wait_for(lk, std::chrono::microseconds(20));
+            } else {
+                cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+            }
+        }
+    }
+};
+
+extern "C" {
+
+int pfsm_server_create(pfsm_server_t **out, pfsm_t *const *hs, int32_t n_automata, int64_t mem_budget,
+                       int32_t max_batch) {
+    if (!out || !hs) return fail(PFSM_EINVAL, "NULL argument");
+    if (n_automata < 1 || n_automata > kMaxBatchAutomata)
+        return fail(PFSM_EINVAL, "n_automata must be in [1, %d]", kMaxBatchAutomata);
+    for (int a = 0; a < n_automata; ++a)
+        if (!hs[a]) return fail(PFSM_EINVAL, "handle %d is NULL", a);
+    if (mem_budget < 1 || max_batch < 1) return fail(PFSM_EINVAL, "mem_budget and max_batch must be >= 1");
+    std::unique_ptr<pfsm_server> sv(new (std::nothrow) pfsm_server);
+    if (!sv) return fail(PFSM_ENOMEM, "server");
+    sv->hs.assign(hs, hs + n_automata);
+    sv->budget = mem_budget;
+    sv->max_batch = max_batch;
+    HIP_TRY(hipGetDevice(&sv->device));
+    for (Slot &sl : sv->slots) {
+        HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    }
+    pfsm_server *p = sv.get();
+    sv->worker = std::thread([p] { p->loop(); });
+    *out = sv.release();
+    return PFSM_OK;
+}
+
+int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n, int64_t *id) {
+    if (!sv || !id || (n > 0 && !bytes)) return fail(PFSM_EINVAL, "NULL argument");
+    if (automaton < 0 || automaton >= (int32_t)sv->hs.size())
+        return fail(PFSM_EINVAL, "automaton %d outside [0, %d)", automaton, (int)sv->hs.size());
+    if (n < 0 || n > kMaxStream) return fail(PFSM_EINVAL, "n must be in [0, 2^31 - 16]");
+    auto r = std::make_unique<Req>();
+    r->aut = automaton;
+    r->bytes.assign(bytes, bytes + n);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stop) return fail(PFSM_EINVAL, "server is shutting down");
+        r->id = sv->next_id++;
+        *id = r->id;
+        sv->queue.push_back(r.get());
+        sv->reqs.emplace(r->id, std::move(r));
+    }
+    sv->cv_work.notify_one();
+    return PFSM_OK;
+}
+
+int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches, int64_t *n_matches) {
+    if (!sv || !matches || !n_matches) return fail(PFSM_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return fail(PFSM_ENOENT, "no request %lld", (long long)id);
+    Req *r = it->second.get();
+    sv->cv_done.wait(lk, [&] { return r->done; });
+    if (r->status != PFSM_OK) return fail(r->status, "request %lld failed", (long long)id);
+    *matches = r->result.data();
+    *n_matches = (int64_t)r->result.size();
+    return PFSM_OK;
+}
+
+int pfsm_server_release(pfsm_server_t *sv, int64_t id) {
+    if (!sv) return fail(PFSM_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return fail(PFSM_ENOENT, "no request %lld", (long long)id);
+    if (!it->second->done) return fail(PFSM_EINVAL, "request %lld is not finished", (long long)id);
+    sv->reqs.erase(it);
+    return PFSM_OK;
+}
+
+int pfsm_server_stats_get(pfsm_server_t *sv, pfsm_server_stats *out) {
+    if (!sv || !out) return fail(PFSM_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *out = sv->st;
+    return PFSM_OK;
+}
+
+void pfsm_server_destroy(pfsm_server_t *sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    for (Slot &sl : sv->slots) sl.release();
+    delete sv;
+}
+
+}  // extern "C"
