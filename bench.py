@@ -42,6 +42,8 @@ def parse():
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batch-replays", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) measurement")
+    ap.add_argument("--serve-requests", type=int, default=3000)
     return ap.parse_args()
 
 
@@ -149,6 +151,67 @@ def batched_vs_plain(replays: int):
             "speedup": round(gbs / plain, 2), "launch": "one HIP graph replay per batch",
             "edits": {"ops": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 2),
                       "p99_ms": round(float(np.percentile(lat, 99)), 2)}}
+
+
+def served(n_req: int):
+    """Served scans: 8 resident automata (4 random 16-state DFAs over abcd, 4
+    NFA unions of 2,000 signatures), requests log-uniform 256 B-4 MiB.  The
+    closed-loop capacity is the throughput with every request queued at once;
+    then requests arrive by a Poisson process at 50 % and 90 % of it.
+    Latency = scheduled arrival -> results on the host (server timestamps)."""
+    import workloads as W
+    import paper_1110_1716_amd as P
+    wl = W.cfg5()
+    hs = [P.pfsm_load(a) for a in wl.automata]
+    rng = W.rng_for(55)
+    sv = P.Server(hs, mem_budget=2 << 30, max_batch=512)
+    for a, x in wl.requests(rng, 32):
+        sv.wait(sv.submit(a, x, borrow=True))
+
+    def closed(reqs):
+        t0 = time.monotonic_ns()
+        ids = [sv.submit(a, x, borrow=True) for a, x in reqs]
+        done = 0
+        for i in ids:
+            sv.wait(i, release=False)
+            done = max(done, sv.times(i)[1])
+            sv.wait(i)
+        return sum(len(x) for _, x in reqs) / ((done - t0) / 1e9)
+
+    def open_loop(reqs, lam):
+        gaps = rng.exponential(1.0 / lam, len(reqs))
+        t0 = time.monotonic_ns() + 2_000_000
+        arr = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
+        ids = []
+        for (a, x), t in zip(reqs, arr):
+            while time.monotonic_ns() < t:
+                pass
+            ids.append(sv.submit(a, x, borrow=True))
+        lat, last = [], 0
+        for i, t in zip(ids, arr):
+            sv.wait(i, release=False)
+            done = sv.times(i)[1]
+            sv.wait(i)
+            lat.append((done - t) / 1e3)
+            last = max(last, done)
+        lat = np.asarray(lat)
+        nbytes = sum(len(x) for _, x in reqs)
+        return {"offered_req_per_s": round(lam, 1), "gbs": round(nbytes / ((last - arr[0]) / 1e9) / 1e9, 3),
+                "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+                "requests": len(reqs)}
+
+    cap_reqs = wl.requests(rng, n_req)
+    mean_bytes = float(np.mean([len(x) for _, x in cap_reqs]))
+    capacity = closed(cap_reqs)
+    res = {"workload": wl.name, "mean_request_bytes": round(mean_bytes), "capacity_gbs": round(capacity / 1e9, 3)}
+    for load in (0.5, 0.9):
+        res[f"load_{int(load * 100)}"] = open_loop(wl.requests(rng, n_req), load * capacity / mean_bytes)
+    res["server"] = sv.stats()
+    res["admission"] = "FIFO into one of two batch slots while bytes + output estimate fit a 2 GiB budget"
+    sv.close()
+    for h in hs:
+        h.free()
+    return res
 
 
 def cpu_baseline(wl, seconds: float):
@@ -278,6 +341,8 @@ def main():
     h.free()
     if not args.no_batch:
         res["batched"] = batched_vs_plain(args.batch_replays)
+    if not args.no_serve:
+        res["served"] = served(args.serve_requests)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -218,8 +218,13 @@ int pfsm_scan_batch_async(pfsm_t *const *hs, int32_t n_automata, const uint8_t *
  * --------------------------------------------------------------------- */
 typedef struct pfsm_server pfsm_server_t;
 
+/* Counters: batches run, reruns (batches that left requests for a later
+ * one), requests finished, their bytes and matches, the largest memory
+ * charge in flight, and the worker's time (ns) packing inputs, enqueueing
+ * batches and delivering results.                                         */
 typedef struct {
     int64_t batches, reruns, requests, bytes, matches, peak_inflight;
+    int64_t pack_ns, launch_ns, deliver_ns;
 } pfsm_server_stats;
 
 /* Start a server over n_automata handles (1..64), which must outlive it and
@@ -230,11 +235,19 @@ int pfsm_server_create(pfsm_server_t **out, pfsm_t *const *hs, int32_t n_automat
 /* Queue a scan of n host bytes (copied during the call) against handle
  * `automaton`; *id names the request.  Errors: PFSM_EINVAL.               */
 int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n, int64_t *id);
+/* pfsm_server_submit without the copy: the server reads `bytes` until the
+ * request is finished, and the caller keeps them unchanged until then.    */
+int pfsm_server_submit_borrowed(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n,
+                                int64_t *id);
 /* Block until request `id` is done; *matches (host memory owned by the
  * server until pfsm_server_release) holds its *n_matches matches in
  * ascending (start, end, label) order.  Errors: PFSM_ENOENT, or the error
  * the request's batch met.                                                */
 int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches, int64_t *n_matches);
+/* When request `id` was submitted and finished (results on the host), in
+ * CLOCK_MONOTONIC nanoseconds; *t_done_ns is 0 while it is not finished.
+ * Errors: PFSM_ENOENT.                                                    */
+int pfsm_server_times(pfsm_server_t *sv, int64_t id, int64_t *t_submit_ns, int64_t *t_done_ns);
 /* Forget a finished request and its matches.  Errors: PFSM_ENOENT,
  * PFSM_EINVAL (not finished).                                             */
 int pfsm_server_release(pfsm_server_t *sv, int64_t id);

@@ -36,8 +36,9 @@ PFSM_ENOSYS = -7
 # Exported symbols of libpfsm.so, as declared in include/pfsm.h.
 EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pattern", "pfsm_scan",
            "pfsm_scan_async", "pfsm_scan_batch", "pfsm_scan_batch_async", "pfsm_last_stats", "pfsm_free",
-           "pfsm_strerror", "pfsm_last_error", "pfsm_server_create", "pfsm_server_submit", "pfsm_server_wait",
-           "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy")
+           "pfsm_strerror", "pfsm_last_error", "pfsm_server_create", "pfsm_server_submit", "pfsm_server_submit_borrowed",
+           "pfsm_server_wait",
+           "pfsm_server_times", "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy")
 
 
 class PfsmError(RuntimeError):
@@ -66,7 +67,8 @@ class _Stats(ctypes.Structure):
 
 class _ServerStats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_int64), ("reruns", ctypes.c_int64), ("requests", ctypes.c_int64),
-                ("bytes", ctypes.c_int64), ("matches", ctypes.c_int64), ("peak_inflight", ctypes.c_int64)]
+                ("bytes", ctypes.c_int64), ("matches", ctypes.c_int64), ("peak_inflight", ctypes.c_int64),
+                ("pack_ns", ctypes.c_int64), ("launch_ns", ctypes.c_int64), ("deliver_ns", ctypes.c_int64)]
 
 
 _lib = None
@@ -96,7 +98,9 @@ def load_library(path: str = LIB_PATH):
         "pfsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "pfsm_server_create": (ctypes.c_int, [ctypes.POINTER(vp), vp, i32, i64, i32]),
         "pfsm_server_submit": (ctypes.c_int, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+        "pfsm_server_submit_borrowed": (ctypes.c_int, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
         "pfsm_server_wait": (ctypes.c_int, [vp, i64, ctypes.POINTER(vp), ctypes.POINTER(i64)]),
+        "pfsm_server_times": (ctypes.c_int, [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "pfsm_server_release": (ctypes.c_int, [vp, i64]),
         "pfsm_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(_ServerStats)]),
         "pfsm_server_destroy": (None, [vp]),
@@ -335,13 +339,21 @@ class Server:
         _check(lib.pfsm_server_create(ctypes.byref(p), arr, len(self._handles), int(mem_budget), int(max_batch)))
         self._ptr = p.value
 
-    def submit(self, automaton: int, data) -> int:
+    def submit(self, automaton: int, data, borrow: bool = False) -> int:
+        """Queue a request.  With borrow=True the server reads ``data`` (a
+        contiguous uint8 array) in place: keep it unchanged until wait()."""
         a = np.ascontiguousarray(np.frombuffer(data, np.uint8) if isinstance(data, (bytes, bytearray))
                                  else np.asarray(data, np.uint8))
         rid = ctypes.c_int64()
-        _check(load_library().pfsm_server_submit(self._ptr, int(automaton), a.ctypes.data if a.size else None,
-                                                 a.size, ctypes.byref(rid)))
+        fn = load_library().pfsm_server_submit_borrowed if borrow else load_library().pfsm_server_submit
+        _check(fn(self._ptr, int(automaton), a.ctypes.data if a.size else None, a.size, ctypes.byref(rid)))
         return rid.value
+
+    def times(self, rid: int) -> Tuple[int, int]:
+        """(submitted, finished) in CLOCK_MONOTONIC ns (time.monotonic_ns)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().pfsm_server_times(self._ptr, int(rid), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def wait(self, rid: int, release: bool = True) -> np.ndarray:
         lib = load_library()

@@ -16,7 +16,8 @@ namespace pfsmk {
 struct Workspace;
 
 constexpr int kMaxBatchAutomata = 64;
-constexpr int64_t kBatchSeg = 65536;  // bytes per segment (both scan kernels)
+constexpr int64_t kBatchSegMax = 65536;  // bytes per segment (both scan kernels)
+constexpr int64_t kBatchSegMin = 4096;
 
 // What the device reports back about a batch.
 struct BatchInfo {
@@ -31,12 +32,14 @@ struct BatchPlanArgs {
     const int64_t *stream_off;  // [n_streams + 1]
     const int32_t *stream_aut;  // [n_streams]
     int32_t n_streams, n_aut;
-    int64_t seg, max_stream;
+    int64_t seg_min, seg_max, max_stream;
     int32_t *seg_first;         // [n_streams]
     int32_t *seg_stream;        // [seg_cap]
     int32_t *n_segs;            // [n_aut]
     int32_t *seg_base;          // [n_aut]
     int64_t *bases;             // [n_aut + 1] output index of each launch's first match
+    int64_t *seg;               // [n_aut] bytes per segment of each launch
+    int32_t blocks[kMaxBatchAutomata];  // resident workgroups of each launch's kernel
     int64_t *stream_lo, *stream_hi;  // [n_streams]
     BatchInfo *info;
     int32_t seg_cap, lb_cap;
@@ -60,6 +63,9 @@ hipError_t launch_batch_gather(const BatchGatherArgs &g, hipStream_t s);
 // *info (device memory) once the stream has reached the batch's end.
 struct BatchRun {
     BatchInfo *info = nullptr;
+    const int64_t *stream_lo = nullptr;  // each stream's range in the stage
+    const int64_t *stream_hi = nullptr;
+    int64_t stage_cap = 0;
     int32_t seg_cap = 0;
     int lb_cap = 0;
     std::vector<struct Workspace *> ws;

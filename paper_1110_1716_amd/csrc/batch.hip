@@ -26,18 +26,23 @@ constexpr int PT = 1024;
 
 __global__ __launch_bounds__(PT) void batch_plan_kernel(BatchPlanArgs p) {
     __shared__ int run[kMaxBatchAutomata];
+    __shared__ long long bytes_s[kMaxBatchAutomata];
+    __shared__ long long seg_s[kMaxBatchAutomata];
     __shared__ long long red[PT / 64];
     __shared__ int err_s;
     const int tid = threadIdx.x;
-    if (tid < p.n_aut) run[tid] = 0;
+    if (tid < p.n_aut) {
+        run[tid] = 0;
+        bytes_s[tid] = 0;
+    }
     if (tid == 0) err_s = 0;
     __syncthreads();
+    // Pass 1: validate, clear the stream ranges, sum the bytes per automaton.
     for (int c0 = 0; c0 < p.n_streams; c0 += PT) {
         const int s = c0 + tid;
-        const bool valid = s < p.n_streams;
         int aut = -1;
         int64_t len = 0;
-        if (valid) {
+        if (s < p.n_streams) {
             aut = p.stream_aut[s];
             len = p.stream_off[s + 1] - p.stream_off[s];
             if (aut < 0 || aut >= p.n_aut) err_s = 1;
@@ -45,8 +50,31 @@ __global__ __launch_bounds__(PT) void batch_plan_kernel(BatchPlanArgs p) {
             p.stream_lo[s] = 0;
             p.stream_hi[s] = 0;
         }
+        for (int a = 0; a < p.n_aut; ++a) {
+            const long long t = block_sum<PT>(aut == a && len > 0 ? len : 0, red);
+            if (tid == 0) bytes_s[a] += t;
+        }
+    }
+    __syncthreads();
+    // Segment size of each launch: its bytes over about twice its resident
+    // workgroups, within [seg_min, seg_max], a multiple of 16.
+    if (tid < p.n_aut) {
+        const long long want = 2ll * (p.blocks[tid] > 0 ? p.blocks[tid] : 1);
+        long long sg = (bytes_s[tid] + want - 1) / want;
+        sg = (sg + 15) / 16 * 16;
+        sg = sg < p.seg_min ? p.seg_min : (sg > p.seg_max ? p.seg_max : sg);
+        seg_s[tid] = sg;
+        p.seg[tid] = sg;
+    }
+    __syncthreads();
+    // Pass 2: segments per stream, scanned per automaton in stream order.
+    for (int c0 = 0; c0 < p.n_streams; c0 += PT) {
+        const int s = c0 + tid;
+        const bool valid = s < p.n_streams;
+        const int aut = valid ? p.stream_aut[s] : -1;
+        const int64_t len = valid ? p.stream_off[s + 1] - p.stream_off[s] : 0;
         const bool ok = valid && aut >= 0 && aut < p.n_aut && len > 0 && len <= p.max_stream;
-        const long long nseg = ok ? (len + p.seg - 1) / p.seg : 0;
+        const long long nseg = ok ? (len + seg_s[aut] - 1) / seg_s[aut] : 0;
         for (int a = 0; a < p.n_aut; ++a) {
             long long tot;
             const long long ex = block_excl_scan<PT>(aut == a ? nseg : 0, red, &tot);
@@ -82,7 +110,7 @@ __global__ void batch_fill_kernel(BatchPlanArgs p) {
     const int aut = p.stream_aut[s];
     const int64_t len = p.stream_off[s + 1] - p.stream_off[s];
     if (len <= 0) return;
-    const int nseg = (int)((len + p.seg - 1) / p.seg);
+    const int nseg = (int)((len + p.seg[aut] - 1) / p.seg[aut]);
     const int base = p.seg_base[aut] + p.seg_first[s];
     for (int j = 0; j < nseg; ++j) p.seg_stream[base + j] = s;
 }

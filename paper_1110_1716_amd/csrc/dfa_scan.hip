@@ -386,7 +386,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     __shared__ int mn, ovf, sp_n, seg_s, last_s;
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
-    __shared__ long long ex_s, base_s;
+    __shared__ long long ex_s, base_s, segsz_s;
     __shared__ unsigned epoch_s;
     __shared__ int nsegs_s, segbase_s;
 
@@ -406,6 +406,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         nsegs_s = a.plan.n_segs_dev ? *a.plan.n_segs_dev : a.n_segs;
         segbase_s = a.plan.seg_base_dev ? *a.plan.seg_base_dev : 0;
         base_s = a.plan.base_dev ? *a.plan.base_dev : 0;
+        segsz_s = a.plan.seg_dev ? *a.plan.seg_dev : a.seg;
         mn = 0;
         ovf = 0;
         sp_n = 0;
@@ -421,6 +422,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     }
     const int seg_base = segbase_s;
     const long long out_base = base_s;
+    const int64_t seg_bytes = segsz_s;
     // Tables into LDS: every load of a thread is issued before its stores.
     if (tid < 256) {
         const int f = a.first[tid];
@@ -462,8 +464,8 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         const uint8_t *sx;
         int64_t sn, seg_lo;
         int stream;
-        seg_resolve(a.plan, a.x, a.n, a.seg, sg, seg_base, sx, sn, seg_lo, stream);
-        const int64_t seg_hi = seg_lo + a.seg < sn ? seg_lo + a.seg : sn;
+        seg_resolve(a.plan, a.x, a.n, seg_bytes, sg, seg_base, sx, sn, seg_lo, stream);
+        const int64_t seg_hi = seg_lo + seg_bytes < sn ? seg_lo + seg_bytes : sn;
         // Shifted positions: p = stream position + dsh, bytes of xa.
         const int dsh = (int)(reinterpret_cast<uintptr_t>(sx) & 15);
         c.xa = sx - dsh;

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     __shared__ int sh[16];
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
-    __shared__ long long ex_s, base_s;
+    __shared__ long long ex_s, base_s, segsz_s;
     __shared__ unsigned epoch_s;
 
     const int tid = threadIdx.x;
@@ -472,6 +472,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         nsegs_s = a.plan.n_segs_dev ? *a.plan.n_segs_dev : a.n_segs;
         segbase_s = a.plan.seg_base_dev ? *a.plan.seg_base_dev : 0;
         base_s = a.plan.base_dev ? *a.plan.base_dev : 0;
+        segsz_s = a.plan.seg_dev ? *a.plan.seg_dev : a.seg;
         mn = 0;
         ovf = 0;
         nbig = 0;
@@ -486,6 +487,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     }
     const int seg_base = segbase_s;
     const long long out_base = base_s;
+    const int64_t seg_bytes = segsz_s;
     if (a.pair_on)
         for (int i = tid; i < 2048; i += NT) pbits_s[i] = a.p_bits[i];
     for (int i = tid; i < 257; i += NT) {
@@ -522,8 +524,8 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         const uint8_t *sx;
         int64_t sn, seg_lo;
         int stream;
-        seg_resolve(a.plan, a.x, a.n, a.seg, sg, seg_base, sx, sn, seg_lo, stream);
-        const int64_t seg_hi = seg_lo + a.seg < sn ? seg_lo + a.seg : sn;
+        seg_resolve(a.plan, a.x, a.n, seg_bytes, sg, seg_base, sx, sn, seg_lo, stream);
+        const int64_t seg_hi = seg_lo + seg_bytes < sn ? seg_lo + seg_bytes : sn;
         // Shifted positions: p = stream position + dsh, byte p of xa.
         const int dsh = (int)(reinterpret_cast<uintptr_t>(sx) & 15);
         c.xa = sx - dsh;

@@ -48,6 +48,7 @@ struct SegPlan {
     const int32_t *n_segs_dev;  // segments of this launch
     const int32_t *seg_base_dev;
     const int64_t *base_dev;    // output index of this launch's first match
+    const int64_t *seg_dev;     // bytes per segment of this launch
     int64_t *stream_lo;         // [n_streams] each stream's range in the output
     int64_t *stream_hi;
 };

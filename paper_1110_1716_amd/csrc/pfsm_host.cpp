@@ -479,10 +479,10 @@ namespace {
 // Device buffers of batched scans on one stream (kept for the process).
 struct BatchWs {
     int32_t *seg_first = nullptr, *seg_stream = nullptr, *n_segs = nullptr, *seg_base = nullptr;
-    int64_t *bases = nullptr, *stream_lo = nullptr, *stream_hi = nullptr;
+    int64_t *bases = nullptr, *seg = nullptr, *stream_lo = nullptr, *stream_hi = nullptr;
     MatchOut *stage = nullptr;
     BatchInfo *info = nullptr, *h_info = nullptr;  // h_info: pinned
-    int64_t c_first = 0, c_seg = 0, c_nsegs = 0, c_base = 0, c_bases = 0, c_lo = 0, c_hi = 0, c_stage = 0;
+    int64_t c_first = 0, c_seg = 0, c_nsegs = 0, c_base = 0, c_bases = 0, c_lo = 0, c_hi = 0, c_stage = 0, c_segsz = 0;
 };
 
 std::mutex g_batch_mu;
@@ -549,10 +549,12 @@ static int batch_enqueue(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d
     int rc = batch_ws(s, &bw);
     if (rc) return rc;
     const int64_t ns = std::max(n_streams, 1);
-    const int64_t need[8] = {ns, ns, ns, n_automata, n_automata, n_automata + 1, std::max<int64_t>(cap, 1), 4 * ns + 4096};
-    const int64_t have[8] = {bw->c_first, bw->c_lo, bw->c_hi, bw->c_nsegs, bw->c_base, bw->c_bases, bw->c_stage, bw->c_seg};
+    const int64_t need[9] = {ns, ns, ns, n_automata, n_automata, n_automata + 1, std::max<int64_t>(cap, 1), 4 * ns + 4096,
+                             n_automata};
+    const int64_t have[9] = {bw->c_first, bw->c_lo, bw->c_hi, bw->c_nsegs, bw->c_base, bw->c_bases, bw->c_stage, bw->c_seg,
+                             bw->c_segsz};
     if (!may_grow) {
-        for (int k = 0; k < 7; ++k)
+        for (int k = 0; k < 9; ++k)
             if (have[k] < need[k])
                 return fail(PFSM_ENOMEM, "batch buffers are smaller than this batch needs: run pfsm_scan_batch "
                                          "with the same sizes once first");
@@ -565,6 +567,7 @@ static int batch_enqueue(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d
         if ((rc = grow(&bw->bases, &bw->c_bases, need[5], s))) return rc;
         if ((rc = grow(&bw->stage, &bw->c_stage, need[6], s))) return rc;
         if ((rc = grow(&bw->seg_stream, &bw->c_seg, need[7], s))) return rc;
+        if ((rc = grow(&bw->seg, &bw->c_segsz, need[8], s))) return rc;
     }
     ws.assign(n_automata, nullptr);
     for (int a = 0; a < n_automata; ++a) {
@@ -579,8 +582,12 @@ static int batch_enqueue(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d
     p.stream_aut = d_stream_automaton;
     p.n_streams = n_streams;
     p.n_aut = n_automata;
-    p.seg = kBatchSeg;
+    p.seg_min = kBatchSegMin;
+    p.seg_max = kBatchSegMax;
     p.max_stream = kMaxStream;
+    p.seg = bw->seg;
+    for (int a = 0; a < n_automata; ++a)
+        p.blocks[a] = hs[a]->kind == 1 ? nfa_grid_blocks(hs[a]->nfa.get()) : hs[a]->n_blocks;
     p.seg_first = bw->seg_first;
     p.seg_stream = bw->seg_stream;
     p.n_segs = bw->n_segs;
@@ -601,12 +608,13 @@ static int batch_enqueue(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d
         sp.n_segs_dev = bw->n_segs + a;
         sp.seg_base_dev = bw->seg_base + a;
         sp.base_dev = bw->bases + a;
+        sp.seg_dev = bw->seg + a;
         sp.stream_lo = bw->stream_lo;
         sp.stream_hi = bw->stream_hi;
         pfsm_t *h = hs[a];
-        rc = h->kind == 1 ? nfa_launch(h->nfa.get(), d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage,
+        rc = h->kind == 1 ? nfa_launch(h->nfa.get(), d_data, 0, &sp, kBatchSegMax, bw->stage, bw->c_stage,
                                        bw->bases + a + 1, s)
-                          : dfa_launch(h, d_data, 0, &sp, kBatchSeg, bw->stage, bw->c_stage, bw->bases + a + 1, s);
+                          : dfa_launch(h, d_data, 0, &sp, kBatchSegMax, bw->stage, bw->c_stage, bw->bases + a + 1, s);
         if (rc) return rc;
     }
     BatchGatherArgs g{};
@@ -643,6 +651,9 @@ int batch_run(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data, cons
     if (rc) return rc;
     run->bw = bw;
     run->info = bw->info;
+    run->stream_lo = bw->stream_lo;
+    run->stream_hi = bw->stream_hi;
+    run->stage_cap = bw->c_stage;
     return PFSM_OK;
 }
 

@@ -11,6 +11,7 @@
 // handed to the waiting callers.  A batch whose output outgrows the
 // estimate is run again at the exact size (the total is known by then).
 #include <hip/hip_runtime.h>
+#include <time.h>
 
 #include <algorithm>
 #include <atomic>
@@ -18,9 +19,11 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -33,15 +36,94 @@ using namespace pfsmk;
 namespace {
 
 constexpr int kSlots = 2;
+constexpr int64_t kBatchBytes = 32ll << 20;  // input bytes per batch (two batches pipeline)
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
+}
 
 struct Req {
     int64_t id = 0;
+    int64_t t_submit = 0, t_done = 0;  // CLOCK_MONOTONIC ns
     int32_t aut = 0;
-    std::vector<uint8_t> bytes;
+    std::vector<uint8_t> bytes;  // a copy, or empty when borrowed
+    const uint8_t *src = nullptr;  // the request's bytes (bytes.data() or the caller's)
+    int64_t n = 0;
+    int64_t exact = -1;  // its match count, once a batch has counted it
     std::vector<pfsm_match_t> result;
     int status = PFSM_OK;
     bool done = false;
 };
+
+// Threads that share the host copies of a batch (packing inputs, handing
+// out results): run(n, f) calls f(0..n-1) on the pool and the caller.
+class CopyPool {
+  public:
+    explicit CopyPool(int n_threads) {
+        for (int t = 0; t < n_threads; ++t) th_.emplace_back([this] { loop(); });
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    void run(int n, const std::function<void(int)> &f) {
+        if (n <= 0) return;
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            f_ = &f;
+            n_ = n;
+            next_ = 0;
+            done_ = 0;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(m_);
+        cv_done_.wait(lk, [&] { return done_ == n_; });
+        f_ = nullptr;
+    }
+
+  private:
+    void work() {
+        for (;;) {
+            int i;
+            const std::function<void(int)> *f;
+            {
+                std::lock_guard<std::mutex> lk(m_);
+                if (!f_ || next_ >= n_) return;
+                i = next_++;
+                f = f_;
+            }
+            (*f)(i);
+            std::lock_guard<std::mutex> lk(m_);
+            if (++done_ == n_) cv_done_.notify_all();
+        }
+    }
+    void loop() {
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return stop_ || (f_ && next_ < n_); });
+                if (stop_) return;
+            }
+            work();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, cv_done_;
+    const std::function<void(int)> *f_ = nullptr;
+    int n_ = 0, next_ = 0, done_ = 0;
+    bool stop_ = false;
+};
+
+constexpr int kCopyThreads = 7;         // helpers besides the worker
+constexpr int64_t kCopyChunk = 1 << 20;  // bytes per copy task
 
 // A buffer that only grows (contents are not kept).
 struct Buf {
@@ -77,12 +159,13 @@ struct Slot {
     int64_t bytes = 0;    // input bytes of this batch
     int64_t out_cap = 0;  // output rows reserved for it
     Buf h_data{nullptr, 0, true}, h_off{nullptr, 0, true}, h_aut{nullptr, 0, true}, h_moff{nullptr, 0, true},
-        h_out{nullptr, 0, true}, h_info{nullptr, 0, true};
+        h_out{nullptr, 0, true}, h_info{nullptr, 0, true}, h_lohi{nullptr, 0, true};
     Buf d_data, d_off, d_aut, d_moff, d_out;
     BatchRun run;
 
     void release() {
-        for (Buf *b : {&h_data, &h_off, &h_aut, &h_moff, &h_out, &h_info, &d_data, &d_off, &d_aut, &d_moff, &d_out})
+        for (Buf *b : {&h_data, &h_off, &h_aut, &h_moff, &h_out, &h_info, &h_lohi, &d_data, &d_off, &d_aut, &d_moff,
+                       &d_out})
             b->release();
         if (ev) (void)hipEventDestroy(ev);
         if (stream) (void)hipStreamDestroy(stream);
@@ -108,8 +191,35 @@ struct pfsm_server {
     std::thread worker;
     int64_t inflight = 0;  // bytes charged to busy slots (worker thread only)
     pfsm_server_stats st{};
+    std::vector<double> density;  // matches per byte seen so far, per automaton (worker only)
+    std::unique_ptr<CopyPool> pool;
 
-    static int64_t out_estimate(int64_t n) { return n / 16 + 256; }
+    // Copy many (dst, src, bytes) pieces, split in chunks over the pool.
+    void copy_all(const std::vector<std::tuple<void *, const void *, int64_t>> &parts) {
+        std::vector<std::tuple<char *, const char *, int64_t>> chunks;
+        int64_t total = 0;
+        for (auto &p : parts) {
+            char *d = static_cast<char *>(std::get<0>(p));
+            const char *s = static_cast<const char *>(std::get<1>(p));
+            for (int64_t o = 0; o < std::get<2>(p); o += kCopyChunk)
+                chunks.emplace_back(d + o, s + o, std::min(kCopyChunk, std::get<2>(p) - o));
+            total += std::get<2>(p);
+        }
+        if (total < (4 << 20)) {
+            for (auto &c : chunks) std::memcpy(std::get<0>(c), std::get<1>(c), (size_t)std::get<2>(c));
+            return;
+        }
+        pool->run((int)chunks.size(), [&](int i) {
+            std::memcpy(std::get<0>(chunks[i]), std::get<1>(chunks[i]), (size_t)std::get<2>(chunks[i]));
+        });
+    }
+
+    // Output rows to reserve for a request: its count when a batch has
+    // counted it, else its automaton's density so far with a margin.
+    int64_t out_estimate(const Req *r) const {
+        if (r->exact >= 0) return r->exact;
+        return (int64_t)((double)r->n * density[r->aut] * 1.5) + 256;
+    }
     static int64_t charge(int64_t bytes, int64_t out_rows) {
         return bytes + out_rows * (int64_t)(sizeof(pfsm_match_t) * 2);
     }
@@ -117,8 +227,10 @@ struct pfsm_server {
     void finish(Slot &sl, int status) {
         {
             std::lock_guard<std::mutex> lk(mu);
+            const int64_t t = now_ns();
             for (Req *r : sl.reqs) {
                 if (status != PFSM_OK) r->status = status;
+                r->t_done = t;
                 r->done = true;
             }
             st.requests += (int64_t)sl.reqs.size();
@@ -144,15 +256,20 @@ struct pfsm_server {
         if ((rc = sl.d_aut.reserve(4 * nr))) return rc;
         if ((rc = sl.d_out.reserve(sl.out_cap * (int64_t)sizeof(MatchOut)))) return rc;
         if ((rc = sl.h_info.reserve(sizeof(BatchInfo)))) return rc;
+        const int64_t t0 = now_ns();
         int64_t pos = 0;
+        std::vector<std::tuple<void *, const void *, int64_t>> parts;
+        parts.reserve(nr);
         for (int64_t j = 0; j < nr; ++j) {
             Req *r = sl.reqs[j];
             sl.h_off.as<int64_t>()[j] = pos;
             sl.h_aut.as<int32_t>()[j] = r->aut;
-            if (!r->bytes.empty()) std::memcpy(sl.h_data.as<uint8_t>() + pos, r->bytes.data(), r->bytes.size());
-            pos += (int64_t)r->bytes.size();
+            if (r->n) parts.emplace_back(sl.h_data.as<uint8_t>() + pos, r->src, r->n);
+            pos += r->n;
         }
+        copy_all(parts);
         sl.h_off.as<int64_t>()[nr] = pos;
+        const int64_t t1 = now_ns();
         if (pos) HIP_TRY(hipMemcpyAsync(sl.d_data.p, sl.h_data.p, pos, hipMemcpyHostToDevice, sl.stream));
         HIP_TRY(hipMemcpyAsync(sl.d_off.p, sl.h_off.p, 8 * (nr + 1), hipMemcpyHostToDevice, sl.stream));
         HIP_TRY(hipMemcpyAsync(sl.d_aut.p, sl.h_aut.p, 4 * nr, hipMemcpyHostToDevice, sl.stream));
@@ -165,23 +282,20 @@ struct pfsm_server {
         HIP_TRY(hipEventRecord(sl.ev, sl.stream));
         std::lock_guard<std::mutex> lk(mu);
         ++st.batches;
+        st.pack_ns += t1 - t0;
+        st.launch_ns += now_ns() - t1;
         return PFSM_OK;
     }
 
-    // The slot's batch has finished: deliver its results, or run it again.
+    // The slot's batch has finished: deliver the results of every request
+    // whose matches are all in the output; the others (the output estimate
+    // was short) go back to the front of the queue with their exact count.
     int complete(Slot &sl) {
         const int64_t nr = (int64_t)sl.reqs.size();
         const BatchInfo info = *sl.h_info.as<BatchInfo>();
         bool again = false;
         int rc = batch_fit(&sl.run, info, sl.stream, &again);
         if (rc) return rc;
-        const int64_t *mo = sl.h_moff.as<int64_t>();
-        const int64_t total = mo[nr];
-        if (!again && total > sl.out_cap) {
-            inflight += charge(0, total - sl.out_cap);
-            sl.out_cap = total;
-            again = true;
-        }
         if (again) {
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -189,18 +303,59 @@ struct pfsm_server {
             }
             return launch(sl);
         }
-        if ((rc = sl.h_out.reserve(std::max<int64_t>(total, 1) * (int64_t)sizeof(pfsm_match_t)))) return rc;
-        if (total) {
-            HIP_TRY(hipMemcpyAsync(sl.h_out.p, sl.d_out.p, total * sizeof(pfsm_match_t), hipMemcpyDeviceToHost,
+        const int64_t *mo = sl.h_moff.as<int64_t>();
+        const int64_t total = mo[nr];
+        std::vector<char> whole(nr, 1);
+        if (total > sl.out_cap) {
+            // a request is whole when its output rows and its stage rows fit
+            if ((rc = sl.h_lohi.reserve(16 * nr))) return rc;
+            int64_t *hi = sl.h_lohi.as<int64_t>();
+            HIP_TRY(hipMemcpyAsync(hi, sl.run.stream_hi, 8 * nr, hipMemcpyDeviceToHost, sl.stream));
+            HIP_TRY(hipStreamSynchronize(sl.stream));
+            for (int64_t j = 0; j < nr; ++j) whole[j] = mo[j + 1] <= sl.out_cap && hi[j] <= sl.run.stage_cap;
+        }
+        const int64_t t0 = now_ns();
+        const int64_t got = std::min(total, sl.out_cap);
+        if ((rc = sl.h_out.reserve(std::max<int64_t>(got, 1) * (int64_t)sizeof(pfsm_match_t)))) return rc;
+        if (got) {
+            HIP_TRY(hipMemcpyAsync(sl.h_out.p, sl.d_out.p, got * sizeof(pfsm_match_t), hipMemcpyDeviceToHost,
                                    sl.stream));
             HIP_TRY(hipStreamSynchronize(sl.stream));
         }
         const pfsm_match_t *m = sl.h_out.as<pfsm_match_t>();
-        for (int64_t j = 0; j < nr; ++j) sl.reqs[j]->result.assign(m + mo[j], m + mo[j + 1]);
+        std::vector<Req *> redo;
+        std::vector<Req *> done;
+        std::vector<std::tuple<void *, const void *, int64_t>> parts;
+        for (int64_t j = 0; j < nr; ++j) {
+            Req *r = sl.reqs[j];
+            const int64_t k = mo[j + 1] - mo[j];
+            if (r->n > 0) {
+                const double d = (double)k / (double)r->n;
+                density[r->aut] = std::max(d, 0.8 * density[r->aut] + 0.2 * d);
+            }
+            if (whole[j]) {
+                r->result.resize(k);
+                if (k) parts.emplace_back(r->result.data(), m + mo[j], k * (int64_t)sizeof(pfsm_match_t));
+                done.push_back(r);
+            } else {
+                r->exact = k;
+                redo.push_back(r);
+            }
+        }
+        copy_all(parts);
+        if (!redo.empty()) {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto it = redo.rbegin(); it != redo.rend(); ++it) queue.push_front(*it);
+            ++st.reruns;
+        }
+        int64_t delivered = 0;
+        for (Req *r : done) delivered += (int64_t)r->result.size();
         {
             std::lock_guard<std::mutex> lk(mu);
-            st.matches += total;
+            st.matches += delivered;
+            st.deliver_ns += now_ns() - t0;
         }
+        sl.reqs.swap(done);
         finish(sl, PFSM_OK);
         return PFSM_OK;
     }
@@ -212,8 +367,10 @@ struct pfsm_server {
         int64_t bytes = 0, rows = 0;
         while (!queue.empty() && (int32_t)sl.reqs.size() < max_batch) {
             Req *r = queue.front();
-            const int64_t n = (int64_t)r->bytes.size();
-            const int64_t add = charge(bytes + n, rows + out_estimate(n)) - charge(bytes, rows);
+            const int64_t n = r->n;
+            if (!sl.reqs.empty() && bytes + n > kBatchBytes) break;
+            const int64_t est = out_estimate(r);
+            const int64_t add = charge(bytes + n, rows + est) - charge(bytes, rows);
             // the first request of a batch is admitted when nothing else is in
             // flight, so a request larger than the budget still runs
             const bool first_alone = sl.reqs.empty() && inflight == 0;
@@ -221,7 +378,7 @@ struct pfsm_server {
             queue.pop_front();
             sl.reqs.push_back(r);
             bytes += n;
-            rows += out_estimate(n);
+            rows += est;
         }
         if (sl.reqs.empty()) return false;
         sl.bytes = bytes;
@@ -277,6 +434,8 @@ int pfsm_server_create(pfsm_server_t **out, pfsm_t *const *hs, int32_t n_automat
     std::unique_ptr<pfsm_server> sv(new (std::nothrow) pfsm_server);
     if (!sv) return fail(PFSM_ENOMEM, "server");
     sv->hs.assign(hs, hs + n_automata);
+    sv->density.assign(n_automata, 1.0 / 16);
+    sv->pool = std::make_unique<CopyPool>(kCopyThreads);
     sv->budget = mem_budget;
     sv->max_batch = max_batch;
     HIP_TRY(hipGetDevice(&sv->device));
@@ -290,14 +449,22 @@ int pfsm_server_create(pfsm_server_t **out, pfsm_t *const *hs, int32_t n_automat
     return PFSM_OK;
 }
 
-int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n, int64_t *id) {
+static int server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n, int64_t *id,
+                         bool copy) {
     if (!sv || !id || (n > 0 && !bytes)) return fail(PFSM_EINVAL, "NULL argument");
     if (automaton < 0 || automaton >= (int32_t)sv->hs.size())
         return fail(PFSM_EINVAL, "automaton %d outside [0, %d)", automaton, (int)sv->hs.size());
     if (n < 0 || n > kMaxStream) return fail(PFSM_EINVAL, "n must be in [0, 2^31 - 16]");
     auto r = std::make_unique<Req>();
+    r->t_submit = now_ns();
     r->aut = automaton;
-    r->bytes.assign(bytes, bytes + n);
+    r->n = n;
+    if (copy) {
+        r->bytes.assign(bytes, bytes + n);
+        r->src = r->bytes.data();
+    } else {
+        r->src = bytes;
+    }
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         if (sv->stop) return fail(PFSM_EINVAL, "server is shutting down");
@@ -310,6 +477,15 @@ int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *byte
     return PFSM_OK;
 }
 
+int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n, int64_t *id) {
+    return server_submit(sv, automaton, bytes, n, id, true);
+}
+
+int pfsm_server_submit_borrowed(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n,
+                                int64_t *id) {
+    return server_submit(sv, automaton, bytes, n, id, false);
+}
+
 int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches, int64_t *n_matches) {
     if (!sv || !matches || !n_matches) return fail(PFSM_EINVAL, "NULL argument");
     std::unique_lock<std::mutex> lk(sv->mu);
@@ -320,6 +496,16 @@ int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches
     if (r->status != PFSM_OK) return fail(r->status, "request %lld failed", (long long)id);
     *matches = r->result.data();
     *n_matches = (int64_t)r->result.size();
+    return PFSM_OK;
+}
+
+int pfsm_server_times(pfsm_server_t *sv, int64_t id, int64_t *t_submit_ns, int64_t *t_done_ns) {
+    if (!sv || !t_submit_ns || !t_done_ns) return fail(PFSM_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return fail(PFSM_ENOENT, "no request %lld", (long long)id);
+    *t_submit_ns = it->second->t_submit;
+    *t_done_ns = it->second->done ? it->second->t_done : 0;
     return PFSM_OK;
 }
 

@@ -531,3 +531,57 @@ def cfg4(seed: int = 4, n_streams: int = 4096, len_lo: int = 64, len_hi: int = M
                          f"({'/'.join(str(int(n)) for n in dfa_states)} states) and an NFA union of "
                          f"{n_patterns} signatures", automata, data, off, aut, seed, ops,
                          {"nfa_index": nfa_idx, "signatures": sigs, "perm": perm})
+
+
+@dataclass
+class ServeWorkload:
+    name: str
+    automata: list  # 4 small byte-mapped DFAs, then 4 NFA unions
+    pools: list  # per automaton: request payload buffers to slice from
+    seed: int
+    len_lo: int
+    len_hi: int
+    meta: dict = field(default_factory=dict)
+
+    def requests(self, rng: np.random.Generator, n: int):
+        """n requests: (automaton, bytes) with a uniformly drawn automaton and a
+        length log-uniform on [len_lo, len_hi], cut from that automaton's pool."""
+        out = []
+        for _ in range(n):
+            a = int(rng.integers(0, len(self.automata)))
+            k = int(np.exp(rng.uniform(np.log(self.len_lo), np.log(self.len_hi))))
+            buf = self.pools[a][int(rng.integers(0, len(self.pools[a])))]
+            at = int(rng.integers(0, buf.size - k + 1))
+            out.append((a, buf[at:at + k]))
+        return out
+
+
+def cfg5(seed: int = 5, len_lo: int = 256, len_hi: int = 4 * MiB, n_patterns: int = 2000,
+         pool_per_automaton: int = 4) -> ServeWorkload:
+    """Served scans: 8 resident automata (the cfg1 recipe with seeds 5-8, the
+    cfg3 NFA recipe with seeds 9-12); requests log-uniform on [256 B, 4 MiB]
+    (mean about 432 KB), bytes over 'abcd' for the DFAs and Zipf(1.1) bytes
+    for the NFAs (each NFA's own byte permutation, instances planted at 1e-4
+    per byte).  Payloads are slices of per-automaton pools of len_hi bytes."""
+    automata, pools = [], []
+    for sd in range(seed, seed + 4):
+        automata.append(cfg1(seed=sd).automaton)
+        rng = rng_for(1000 + sd)
+        pools.append([(rng.integers(0, 4, len_hi) + ord("a")).astype(np.uint8) for _ in range(pool_per_automaton)])
+    for sd in range(seed + 4, seed + 8):
+        rng = rng_for(sd)
+        sigs = signature_union(rng, n_patterns)
+        automata.append(union_nfa(sigs))
+        perm = rng.permutation(256).astype(np.uint8)
+        bufs = []
+        for _ in range(pool_per_automaton):
+            x = zipf_bytes(rng, len_hi, perm=perm)
+            for _ in range(int(len_hi * 1e-4)):
+                w = _instance_bytes(rng, sigs[int(rng.integers(0, len(sigs)))], 64, perm)
+                at = int(rng.integers(0, len_hi - w.size + 1))
+                x[at:at + w.size] = w
+            bufs.append(x)
+        pools.append(bufs)
+    return ServeWorkload("8 resident automata (4 random DFAs of 16 states over abcd, 4 NFA unions of "
+                         f"{n_patterns} signatures); requests log-uniform {len_lo} B-{len_hi >> 20} MiB",
+                         automata, pools, seed, len_lo, len_hi)
