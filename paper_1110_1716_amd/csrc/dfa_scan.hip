@@ -338,20 +338,6 @@ __device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32
     return cnt;
 }
 
-// Exclusive prefix over the wave of a count in [0, 16), and the wave total.
-__device__ __forceinline__ int wave_excl_small(int v, int &total) {
-    const unsigned long long below = lanes_below();
-    int ex = 0, tot = 0;
-#pragma unroll
-    for (int bit = 0; bit < 4; ++bit) {
-        const unsigned long long m = __ballot((v >> bit) & 1);
-        ex += __popcll(m & below) << bit;
-        tot += __popcll(m) << bit;
-    }
-    total = tot;
-    return ex;
-}
-
 // Move the walks of this wave's queue to the workgroup's spill area in
 // memory (stores only).  Returns false when the area is full: the segment is
 // then re-walked at its end and the walks are dropped.

@@ -129,15 +129,12 @@ __device__ __forceinline__ bool add_target(const NfaArgs &a, uint32_t (&O)[K], i
     return ok;
 }
 
-// One symbol for a set: O = closure(delta(S, byte)) over live states.
-// Returns false when O would exceed K states.
-__device__ __forceinline__ bool nfa_step(const NfaArgs &a, const uint32_t (&S)[K], int nS, int byte,
-                                         uint32_t (&O)[K], int &nO) {
+// One symbol for a set whose state records are already loaded:
+// O = closure(delta(S, byte)) over live states.  Returns false when O would
+// exceed K states.
+__device__ __forceinline__ bool nfa_step_rec(const NfaArgs &a, const NfaRec (&r)[K], int nS, int byte,
+                                             uint32_t (&O)[K], int &nO) {
     nO = 0;
-    NfaRec r[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-        if (j < nS) r[j] = a.rec[S[j] & kStateMask];
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -155,6 +152,17 @@ __device__ __forceinline__ bool nfa_step(const NfaArgs &a, const uint32_t (&S)[K
         }
     }
     return ok;
+}
+
+// One symbol for a set: O = closure(delta(S, byte)) over live states.
+// Returns false when O would exceed K states.
+__device__ __forceinline__ bool nfa_step(const NfaArgs &a, const uint32_t (&S)[K], int nS, int byte,
+                                         uint32_t (&O)[K], int &nO) {
+    NfaRec r[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < nS) r[j] = a.rec[S[j] & kStateMask];
+    return nfa_step_rec(a, r, nS, byte, O, nO);
 }
 
 // Report the labels of the final states of O (ascending, once each).
@@ -450,6 +458,9 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     __shared__ uint32_t pbits_s[2048];
     __shared__ int32_t f1o_s[257];
     __shared__ int32_t e1o_s[257];
+    __shared__ int16_t n1_s[256];   // states after the first symbol, by byte
+    __shared__ int16_t e1n_s[256];  // labels reported after the first symbol, by byte
+    __shared__ uint32_t lst_all[(NT / 64) * 512];
     __shared__ Walk qall[(NT / 64) * QW];
     __shared__ uint32_t mkey[MC];
     __shared__ int32_t mend[MC];
@@ -495,6 +506,12 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         e1o_s[i] = a.e1_off[i];
     }
     __syncthreads();
+    for (int i = tid; i < 256; i += NT) {
+        const int n1 = f1o_s[i + 1] - f1o_s[i], e1 = e1o_s[i + 1] - e1o_s[i];
+        n1_s[i] = (int16_t)(n1 < 32767 ? n1 : 32767);
+        e1n_s[i] = (int16_t)(e1 < 32767 ? e1 : 32767);
+    }
+    __syncthreads();
     const unsigned epoch = epoch_s;
     const size_t ns = (size_t)a.n_states;
     uint32_t *F0 = a.big_front + (size_t)b * 2 * ns;
@@ -503,6 +520,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
 
     NfaCtx c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf};
     Walk *q = qall + wv * QW;
+    uint32_t *lst = lst_all + wv * 512;
 
     // Replay every listed start with the whole workgroup.
     auto run_big = [&]() __attribute__((always_inline)) {
@@ -546,21 +564,52 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
             const int klo = lo64 <= 0 ? 0 : (lo64 >= 16 ? 16 : (int)lo64);
             const unsigned vmask = ((1u << khi) - 1u) & ~((1u << klo) - 1u);
             const int tail = ((vmask >> 15) & 1u) && i0 + 16 < c.nP ? c.xa[i0 + 16] : 0;
-            for (int k = 0; k < 16; ++k) {
-                bool push = false;
-                Walk ent;
-                ent.n = 0;
-                if ((vmask >> k) & 1u) {
+            // Every start takes its first symbol (and, when the byte pair has
+            // neither states nor labels after two symbols, its second) in
+            // registers; the others are compacted into the wave's list and
+            // taken 64 at a time.
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                unsigned lm = 0;
+                uint32_t ent8[8];
+#pragma unroll
+                for (int k8 = 0; k8 < 8; ++k8) {
+                    const int k = 8 * h + k8;
                     const int32_t i = (int32_t)(i0 + k);
                     const int c1 = byte_of(mine, k);
-                    ++c.T;
-                    const int n1 = f1o_s[c1 + 1] - f1o_s[c1];
-                    if (n1 > 0) {
-                        c.X += n1;
+                    const int c2 = k < 15 ? byte_of(mine, k + 1) : tail;
+                    const int n1 = n1_s[c1];
+                    const int e1 = e1n_s[c1];
+                    const int p = (c1 << 8) | c2;
+                    const bool pb = !a.pair_on || ((pbits_s[p >> 5] >> (p & 31)) & 1u);
+                    const bool valid = (vmask >> k) & 1u;
+                    const bool second = valid && n1 > 0 && i + 1 < n32;
+                    const bool take = valid && n1 > 0 && (e1 > 0 || (second && pb));
+                    c.T += valid ? 1 : 0;
+                    c.X += valid ? n1 : 0;
+                    c.T += (second && !take) ? 1 : 0;
+                    lm |= (take ? 1u : 0u) << k8;
+                    ent8[k8] = (uint32_t)(16 * tid + k) | ((uint32_t)c1 << 12) | ((uint32_t)c2 << 20);
+                }
+                const int cnt = __popc(lm);
+                int total;
+                const int ex = wave_excl_small(cnt, total);
+#pragma unroll
+                for (int k8 = 0; k8 < 8; ++k8)
+                    if ((lm >> k8) & 1u) lst[ex + __popc(lm & ((1u << k8) - 1u))] = ent8[k8];
+                __builtin_amdgcn_wave_barrier();
+                for (int e0 = 0; e0 < total; e0 += 64) {
+                    const int e = e0 + lane;
+                    bool push = false;
+                    Walk ent;
+                    ent.n = 0;
+                    if (e < total) {
+                        const uint32_t w = lst[e];
+                        const int32_t i = (int32_t)(wbase + (w & 4095u));
+                        const int c1 = (int)((w >> 12) & 255u), c2 = (int)(w >> 20);
                         int32_t km = 0;
                         emit_list(c, kBuffer, a.e1, e1o_s[c1], e1o_s[c1 + 1], i, i, km, 0, 0);
                         if (i + 1 < n32) {
-                            const int c2 = k < 15 ? byte_of(mine, k + 1) : tail;
                             int llo, lhi;
                             bool over;
                             const int nS = first_two(c, c1, c2, ent.s, llo, lhi, over);
@@ -582,10 +631,11 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                             }
                         }
                     }
+                    while (qcount > QW - 64) drain_round(c, q, qcount, big_s, &nbig);
+                    const int slot = wave_push_slot(qcount, push);
+                    if (push) q[slot] = ent;
                 }
-                const int slot = wave_push_slot(qcount, push);
-                if (push) q[slot] = ent;
-                while (qcount > QW - 64) drain_round(c, q, qcount, big_s, &nbig);
+                __builtin_amdgcn_wave_barrier();
             }
             // replay list getting full: run it now (uniform decision)
             __syncthreads();

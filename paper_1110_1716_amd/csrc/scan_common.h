@@ -22,6 +22,20 @@ __device__ __forceinline__ int wave_push_slot(int &count, bool pred) {
     return pred ? slot : -1;
 }
 
+// Exclusive prefix over the wave of a count in [0, 16), and the wave total.
+__device__ __forceinline__ int wave_excl_small(int v, int &total) {
+    const unsigned long long below = lanes_below();
+    int ex = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+        const unsigned long long m = __ballot((v >> bit) & 1);
+        ex += __popcll(m & below) << bit;
+        tot += __popcll(m) << bit;
+    }
+    total = tot;
+    return ex;
+}
+
 __device__ __forceinline__ long long wave_sum(long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
