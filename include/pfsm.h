@@ -206,6 +206,41 @@ int pfsm_scan_batch_async(pfsm_t *const *hs, int32_t n_automata, const uint8_t *
                           void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * Streaming scans: chained data partitioning (Section III.D.3).  A stream's
+ * bytes are fed in pieces; every instance still live when a piece ends is
+ * carried into the next one as its start and state set, so the matches of
+ * all pieces together are exactly those of one pfsm_scan of the
+ * concatenated bytes, and no piece re-reads earlier bytes.
+ * --------------------------------------------------------------------- */
+typedef struct pfsm_stream pfsm_stream_t;
+
+/* Open a stream over handle h (which must outlive it) on the current
+ * device.  Editing h afterwards (pfsm_add_pattern, pfsm_remove_pattern)
+ * makes later pieces fail with PFSM_EINVAL.  Errors: PFSM_EINVAL,
+ * PFSM_ENOMEM, PFSM_EHIP.                                                 */
+int pfsm_stream_open(pfsm_stream_t **out, pfsm_t *h);
+
+/* Feed the next n bytes (device memory, any alignment) and report the
+ * matches that END inside them, in ascending (start, end, label) order,
+ * with positions counted from the stream's first byte (starts may lie in
+ * earlier pieces).  The stream's total length must stay below 2^31 - 16.
+ * n == 0 reports nothing and changes nothing.  PFSM_EOVERFLOW: *n_matches
+ * is the exact count, d_out is unspecified, and the stream is left as it
+ * was, so the same piece can be fed again with a larger buffer.
+ * Synchronises `hip_stream`.  A stream is not safe for concurrent use.
+ * Errors: PFSM_EINVAL, PFSM_EOVERFLOW, PFSM_ENOMEM, PFSM_EHIP.            */
+int pfsm_stream_feed(pfsm_stream_t *st, const uint8_t *d_piece, int64_t n, pfsm_match_t *d_out,
+                     int64_t cap, int64_t *n_matches, void *hip_stream);
+
+/* Bytes fed so far (*position) and the number of live instances carried
+ * into the next piece (*n_carried; synchronises `hip_stream`).  Either
+ * pointer may be NULL.  Errors: PFSM_EINVAL, PFSM_EHIP.                   */
+int pfsm_stream_info(pfsm_stream_t *st, int64_t *position, int64_t *n_carried, void *hip_stream);
+
+/* Free the stream (after the device has finished with it).                */
+void pfsm_stream_close(pfsm_stream_t *st);
+
+/* ---------------------------------------------------------------------
  * Serving loop: continuous batching of scan requests (the online use of
  * Section I) against resident handles.  A worker thread admits queued
  * requests, first come first served, into one of two batches while their

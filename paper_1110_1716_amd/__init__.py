@@ -11,7 +11,7 @@ missing, loading fails loudly -- there is no fallback.
 Names follow the C ABI: ``pfsm_load_dfa``, ``pfsm_load_nfa``,
 ``pfsm_add_pattern``, ``pfsm_remove_pattern``, ``pfsm_scan``,
 ``pfsm_scan_async``, ``pfsm_scan_batch``, ``pfsm_scan_batch_async``, ``pfsm_last_stats``,
-``pfsm_free``.
+``pfsm_free``; ``Stream`` wraps ``pfsm_stream_*`` and ``Server`` ``pfsm_server_*``.
 """
 from __future__ import annotations
 
@@ -38,7 +38,8 @@ EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pa
            "pfsm_scan_async", "pfsm_scan_batch", "pfsm_scan_batch_async", "pfsm_last_stats", "pfsm_free",
            "pfsm_strerror", "pfsm_last_error", "pfsm_server_create", "pfsm_server_submit", "pfsm_server_submit_borrowed",
            "pfsm_server_wait",
-           "pfsm_server_times", "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy")
+           "pfsm_server_times", "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy",
+           "pfsm_stream_open", "pfsm_stream_feed", "pfsm_stream_info", "pfsm_stream_close")
 
 
 class PfsmError(RuntimeError):
@@ -105,6 +106,10 @@ def load_library(path: str = LIB_PATH):
         "pfsm_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(_ServerStats)]),
         "pfsm_server_destroy": (None, [vp]),
         "pfsm_last_error": (ctypes.c_char_p, []),
+        "pfsm_stream_open": (ctypes.c_int, [ctypes.POINTER(vp), vp]),
+        "pfsm_stream_feed": (ctypes.c_int, [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp]),
+        "pfsm_stream_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]),
+        "pfsm_stream_close": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -324,6 +329,64 @@ def pfsm_last_stats(h: Pfsm, stream=None) -> dict:
 
 def pfsm_free(h: Pfsm) -> None:
     h.free()
+
+
+class Stream:
+    """A byte stream scanned piece by piece (include/pfsm.h, pfsm_stream_*):
+    the matches reported by all feeds together are those of one pfsm_scan of
+    the concatenated pieces; each feed reports the matches ending inside its
+    piece, positions counted from the stream's first byte."""
+
+    def __init__(self, h: Pfsm):
+        p = ctypes.c_void_p()
+        _check(load_library().pfsm_stream_open(ctypes.byref(p), h.ptr))
+        self._h = h
+        self._ptr = p.value
+
+    def feed(self, x, out=None, stream=None, cap: Optional[int] = None) -> Tuple[int, "torch.Tensor"]:
+        """Feed device bytes ``x``; returns (n_matches, out[:n_matches]).
+        Output handling as in pfsm_scan (an automatic buffer is grown once)."""
+        import torch
+        _check_input(x)
+        lib = load_library()
+        st = _stream_ptr(stream)
+        auto = out is None
+        if auto:
+            cap = cap if cap is not None else x.numel() // 16 + 1024
+            out = torch.empty((cap, 3), dtype=torch.int32, device=x.device)
+        _check_out(out)
+        n = ctypes.c_int64()
+        rc = lib.pfsm_stream_feed(self._ptr, x.data_ptr(), x.numel(), out.data_ptr(), out.shape[0],
+                                  ctypes.byref(n), st)
+        if rc == PFSM_EOVERFLOW and auto:
+            out = torch.empty((n.value, 3), dtype=torch.int32, device=x.device)
+            rc = lib.pfsm_stream_feed(self._ptr, x.data_ptr(), x.numel(), out.data_ptr(), out.shape[0],
+                                      ctypes.byref(n), st)
+        _check(rc)
+        return n.value, out[:n.value]
+
+    def info(self, stream=None) -> Tuple[int, int]:
+        """(bytes fed so far, live instances carried into the next piece)."""
+        pos, car = ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().pfsm_stream_info(self._ptr, ctypes.byref(pos), ctypes.byref(car), _stream_ptr(stream)))
+        return pos.value, car.value
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            load_library().pfsm_stream_close(self._ptr)
+            self._ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

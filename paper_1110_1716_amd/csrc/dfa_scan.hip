@@ -29,6 +29,7 @@
 // writes every buffered match at its rank.  A segment whose matches do not
 // fit the buffer is re-walked 768 starts at a time: count, scan, write.
 #include "scan_common.h"
+#include "stream.h"
 
 namespace pfsmk {
 
@@ -166,6 +167,11 @@ struct DfaCtx {
         k += cnt;
     }
     __device__ __forceinline__ int n_labels(int s) const { return lab_lo(s + 1) - lab_lo(s); }
+    // The instance started at `start` is in live state s after the last byte
+    // of the input: hand it to the next piece when carries are collected.
+    __device__ __forceinline__ void carry(int32_t start, int s) const {
+        if (a.carry.pairs) carry_write(a.carry, carry_reserve(a.carry, 1), start - dsh, (uint32_t)s);
+    }
     // The ring byte of position p (meaningful when p is staged; any p reads
     // inside the ring).
     __device__ __forceinline__ int ring_at(int32_t p) const { return xs[(uint32_t)(p - sl32) & (RING - 1)]; }
@@ -262,6 +268,7 @@ __device__ __forceinline__ bool drain_round(DfaCtx<ENC, kId> &c, QEnt *q, int &q
 #pragma unroll
     for (int j = 0; j < QK; ++j) {
         const bool keep = alive[j] && e[j].pos < c.n32;
+        if (alive[j] && e[j].pos >= c.n32) c.carry(e[j].start, e[j].state);
         again |= keep && c.staged_at((int64_t)(e[j].pos & ~15));
         const int slot = wave_push_slot(nc, keep);
         if (keep) q[slot] = e[j];
@@ -311,6 +318,7 @@ __device__ __forceinline__ bool advance_staged(DfaCtx<ENC, kId> &c, bool act, in
     }
     c.T += nT;
     c.X += nX;
+    if (alive && pos >= c.n32) c.carry(start, s);
     return alive && pos < c.n32;
 }
 
@@ -331,7 +339,10 @@ __device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32
                 p->label = c.lab_at(l);
             }
         }
-        if (++pos >= c.n32) break;
+        if (++pos >= c.n32) {
+            if (!write) c.carry(i, s);
+            break;
+        }
         const int sy = c.sym(c.xa[pos]);
         s = sy < 0 ? -1 : c.live(c.tab(s, sy));
     }
@@ -550,6 +561,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
                     int32_t km = 0;
                     if (act && (c.flag(s1) & kFinal)) c.emit(i, i, s1, km);
                     int32_t pos = i + 1;
+                    if (act && pos >= n32) c.carry(i, s1);
                     const bool park = advance_staged(c, act && pos < n32, i, s1, pos, km, lim);
                     if (qcount > QW - 64 && __any(park)) {
                         // Too many walks wait for the next window: move them
@@ -683,7 +695,58 @@ const void *pick(bool id) {
               : reinterpret_cast<const void *>(&dfa_scan_kernel<ENC, false>);
 }
 
+// Carried instances through a piece, one lane per instance reading the
+// table, flags and labels through the cache hierarchy.  Count pass: matches
+// per instance, and the instances still live after the piece go to the carry
+// list; write pass: the matches, in (end, label) order, from the instance's
+// output offset on.
+__global__ __launch_bounds__(256) void dfa_resume_kernel(DfaResumeArgs r) {
+    const int G = *r.in.n_groups;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+        const unsigned long long key = r.in.keys[r.in.grp_off[g]];
+        const int32_t start = (int32_t)(key >> 32);
+        int s = (int)(uint32_t)key;
+        const long long at = r.write ? r.off[g] : 0;
+        long long k = 0;
+        bool alive = true;
+        for (int64_t p = 0; p < r.n; ++p) {
+            const int b = r.x[p];
+            const int sy = r.identity ? b : (int)r.b2s[b];
+            int t = -1;
+            if (sy >= 0)
+                t = r.tbl16 ? (int)reinterpret_cast<const int16_t *>(r.tbl)[(int64_t)s * r.n_symbols + sy]
+                            : reinterpret_cast<const int32_t *>(r.tbl)[(int64_t)s * r.n_symbols + sy];
+            if (t < 0 || !(r.flags[t] & kLive)) {
+                alive = false;
+                break;
+            }
+            s = t;
+            const int lo = r.lab_off[s], hi = r.lab_off[s + 1];
+            if (r.write) {
+                for (int l = lo; l < hi; ++l, ++k)
+                    if (at + k < r.cap) {
+                        MatchOut *o = &r.out[at + k];
+                        o->start = start;
+                        o->end = r.base + (int32_t)p;
+                        o->label = r.lab[l];
+                    }
+            } else {
+                k += hi - lo;
+            }
+        }
+        if (!r.write) {
+            r.cnt[g] = k;
+            if (alive) carry_write(r.carry, carry_reserve(r.carry, 1), start - r.carry.base, (uint32_t)s);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_dfa_resume(const DfaResumeArgs &r, hipStream_t s) {
+    hipLaunchKernelGGL(dfa_resume_kernel, dim3(64), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
 
 const void *dfa_kernel_fn(int enc, bool identity_map) {
     switch (enc) {

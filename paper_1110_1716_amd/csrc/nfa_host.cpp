@@ -11,6 +11,7 @@
 
 #include "host_common.h"
 #include "pfsm_nfa.h"
+#include "stream.h"
 
 namespace pfsmk {
 
@@ -419,13 +420,14 @@ int nfa_grid_blocks(NfaHost *h) { return h->n_blocks; }
 
 WorkspacePool *nfa_pool(NfaHost *h) { return &h->pool; }
 
-int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
-               int64_t cap, int64_t *d_total, hipStream_t s) {
+namespace {
+
+// The workspace of stream s with replay scratch sized for the current union.
+int nfa_workspace(NfaHost *h, hipStream_t s, Workspace **out) {
     Workspace *w;
     int rc = h->pool.get(s, h->n_blocks, &w);
     if (rc) return rc;
     NfaTables *t = h->tab.get();
-    // replay scratch sized for the current union
     const int64_t words_front = (int64_t)h->n_blocks * 2 * t->n_states;
     const int64_t words_bits = (int64_t)h->n_blocks * ((t->n_states + 31) / 32);
     if (w->big_states < t->n_states) {
@@ -440,10 +442,13 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
         HIP_TRY(hipDeviceSynchronize());
         w->big_states = t->n_states;
     }
-    NfaArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.x = x;
-    a.n = n;
+    *out = w;
+    return PFSM_OK;
+}
+
+// The scan's view of the current tables.
+void nfa_table_args(NfaHost *h, NfaArgs &a) {
+    NfaTables *t = h->tab.get();
     a.n_states = t->n_states;
     a.rec = t->rec.as<NfaRec>();
     a.edges = t->edges.as<uint32_t>();
@@ -461,6 +466,44 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
     a.p_st = t->p_st.as<uint32_t>();
     a.pl_off = t->pl_off.as<int32_t>();
     a.p_lab = t->p_lab.as<int32_t>();
+}
+
+}  // namespace
+
+int nfa_resume(NfaHost *h, const uint8_t *x, int64_t n, int32_t base, const CarrySet &in, int64_t *cnt,
+               const int64_t *off, MatchOut *out, int64_t cap, const CarryOut &carry, int write, hipStream_t s) {
+    Workspace *w;
+    int rc = nfa_workspace(h, s, &w);
+    if (rc) return rc;
+    NfaResumeArgs r;
+    std::memset(&r, 0, sizeof r);
+    nfa_table_args(h, r.a);
+    r.a.x = x;
+    r.a.n = n;
+    r.a.out = out;
+    r.a.cap = cap;
+    r.a.big_front = w->big_front;
+    r.a.big_bits = w->big_bits;
+    r.a.carry = carry;
+    r.base = base;
+    r.write = write;
+    r.in = in;
+    r.cnt = cnt;
+    r.off = off;
+    HIP_TRY(launch_nfa_resume(r, h->n_blocks, s));
+    return PFSM_OK;
+}
+
+int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
+               int64_t cap, int64_t *d_total, hipStream_t s, const int64_t *d_base, const CarryOut *carry) {
+    Workspace *w;
+    int rc = nfa_workspace(h, s, &w);
+    if (rc) return rc;
+    NfaArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.x = x;
+    a.n = n;
+    nfa_table_args(h, a);
     a.out = out;
     a.cap = cap;
     a.total = d_total;
@@ -482,8 +525,10 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
             return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)", (long long)n,
                         (long long)n_segs, w->lb_cap);
         a.n_segs = (int32_t)n_segs;
+        a.plan.base_dev = d_base;
         grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
     }
+    if (carry) a.carry = *carry;
     void *args[] = {&a};
     HIP_TRY(hipLaunchKernel(nfa_kernel_fn(), dim3(grid), dim3(kNfaThreads), args, 0, s));
     w->last_grid = grid;

@@ -27,6 +27,7 @@
 //     segment whose matches overflow the buffer is walked again 256 starts at
 //     a time to count, scan and write.
 #include "scan_common.h"
+#include "stream.h"
 
 namespace pfsmk {
 
@@ -95,6 +96,23 @@ struct NfaCtx {
                 p->label = label;
             }
         }
+    }
+    // The instance started at `start` holds the n states of S after the last
+    // byte of the input: hand it to the next piece when carries are
+    // collected.
+    __device__ __forceinline__ void carry_set(int32_t start, const uint32_t (&S)[K], int n) const {
+        if (!a.carry.pairs) return;
+        const unsigned long long slot = carry_reserve(a.carry, n);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < n) carry_write(a.carry, slot + j, start - dsh, S[j] & kStateMask);
+    }
+    // The same for the set after the first symbol c1 (start = the last byte).
+    __device__ __forceinline__ void carry_first(int32_t start, int c1) const {
+        if (!a.carry.pairs) return;
+        const int lo = f1o_s[c1], hi = f1o_s[c1 + 1];
+        const unsigned long long slot = carry_reserve(a.carry, hi - lo);
+        for (int j = lo; j < hi; ++j) carry_write(a.carry, slot + (j - lo), start - dsh, a.f1[j] & kStateMask);
     }
 };
 
@@ -262,7 +280,10 @@ __device__ __forceinline__ long long walk_lane(NfaCtx &c, int32_t i, int mode, l
     const int n1 = c.f1o_s[c1 + 1] - c.f1o_s[c1];
     if (n1 == 0) return 0;
     emit_list(c, mode, a.e1, c.e1o_s[c1], c.e1o_s[c1 + 1], i, i, k, 0, at);
-    if (i + 1 >= c.n32) return k;
+    if (i + 1 >= c.n32) {
+        if (mode == kCount) c.carry_first(i, c1);
+        return k;
+    }
     uint32_t S[K];
     int llo, lhi;
     bool ovf;
@@ -281,6 +302,7 @@ __device__ __forceinline__ long long walk_lane(NfaCtx &c, int32_t i, int mode, l
         nS = nO;
         ++pos;
     }
+    if (nS > 0 && mode == kCount) c.carry_set(i, S, nS);
     return k;
 }
 
@@ -296,15 +318,89 @@ __device__ __forceinline__ int block_min(int v, int *redi) {
     return m;
 }
 
-// Replay of start s by the whole workgroup with unbounded sets: frontier
-// lists in global scratch, duplicates removed with a visited bitset that is
-// cleared again after every symbol.  Matches before the k0-th are skipped
-// (already reported); work counters are kept for positions >= pos0 (earlier
-// ones were counted).  Returns the number of matches reported from k0 on
-// (every thread).
+// One symbol for a frontier held by the whole workgroup: nxt receives
+// closure(delta(cur, byte)) over live states, duplicate-free (bits marks the
+// states taken and is clear again on return).  Returns the size of nxt on
+// every thread.  Contains barriers; sh[0] must be 0 on entry and is again on
+// return.
+__device__ __forceinline__ int frontier_step(const NfaArgs &a, const uint32_t *cur, int nF, int byte, uint32_t *nxt,
+                                             uint32_t *bits, int *sh) {
+    const int tid = threadIdx.x;
+    for (int j = tid; j < nF; j += NT) {
+        const NfaRec r = a.rec[cur[j] & kStateMask];
+        const int ne = r.n_edges;
+        for (int e = 0; e < ne; ++e) {
+            uint32_t test, tgt;
+            if (r.info & kRecInline) {
+                test = e == 0 ? r.e0_test : r.e1_test;
+                tgt = e == 0 ? r.e0_tgt : r.e1_tgt;
+            } else {
+                const uint2 ed = reinterpret_cast<const uint2 *>(a.edges)[r.edge_off + e];
+                test = ed.x;
+                tgt = ed.y;
+            }
+            if (!edge_matches(a, test, byte)) continue;
+            int lo = 0, hi = 1;
+            if (tgt & kTgtList) {
+                const int idx = (int)(tgt & ~kTgtList);
+                lo = a.cl_off[idx];
+                hi = a.cl_off[idx + 1];
+            }
+            for (int t = lo; t < hi; ++t) {
+                const uint32_t w = (tgt & kTgtList) ? a.cl[t] : tgt;
+                const uint32_t q = w & kStateMask;
+                const uint32_t bit = 1u << (q & 31);
+                const uint32_t old = atomicOr(&bits[q >> 5], bit);
+                if (!(old & bit)) nxt[atomicAdd(&sh[0], 1)] = w;
+            }
+        }
+    }
+    __syncthreads();
+    const int nN = sh[0];
+    __syncthreads();
+    for (int j = tid; j < nN; j += NT) {
+        const uint32_t q = nxt[j] & kStateMask;
+        atomicAnd(&bits[q >> 5], ~(1u << (q & 31)));
+    }
+    if (tid == 0) sh[0] = 0;
+    return nN;
+}
+
+// The labels of the final states of a frontier, ascending and once each:
+// emit(label) runs on every thread for each, in that order.  Contains
+// barriers (sh[1 .. NT/64] are used).
+template <class F>
+__device__ __forceinline__ void frontier_labels(const NfaArgs &a, const uint32_t *front, int nN, int *sh, F &&emit) {
+    const int tid = threadIdx.x;
+    int last = -1;
+    for (;;) {
+        int mine = 0x7fffffff;
+        for (int j = tid; j < nN; j += NT) {
+            if (!(front[j] & kTgtFinal)) continue;
+            const NfaRec r = a.rec[front[j] & kStateMask];
+            const int hi = r.lab_off + (int)(r.info >> 8);
+            for (int l = r.lab_off; l < hi; ++l) {
+                const int v = a.lab[l];
+                if (v > last) {
+                    mine = min(mine, v);
+                    break;
+                }
+            }
+        }
+        const int m = block_min(mine, sh + 1);
+        if (m == 0x7fffffff) break;
+        emit(m);
+        last = m;
+    }
+}
+
+// Replay of start s by the whole workgroup with unbounded sets (frontiers in
+// global scratch).  Matches before the k0-th are skipped (already reported);
+// work counters are kept for positions >= pos0 (earlier ones were counted).
+// Returns the number of matches reported from k0 on (every thread).
 __device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0, int32_t pos0, int mode, long long at,
                                 uint32_t *F0, uint32_t *F1, uint32_t *bits, int *sh) {
-    // sh[0]: next frontier size, sh[1..NT/64]: reduction slots, sh[8]: k
+    // sh[0]: next frontier size, sh[1..NT/64]: reduction slots
     const NfaArgs &a = c.a;
     const int tid = threadIdx.x;
     const int c1 = c.xa[s];
@@ -325,72 +421,15 @@ __device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0
     uint32_t *cur = F0, *nxt = F1;
     int32_t pos = s + 1;
     while (nF > 0 && pos < c.n32) {
-        const int byte = c.xa[pos];
-        for (int j = tid; j < nF; j += NT) {
-            const NfaRec r = a.rec[cur[j] & kStateMask];
-            const int ne = r.n_edges;
-            for (int e = 0; e < ne; ++e) {
-                uint32_t test, tgt;
-                if (r.info & kRecInline) {
-                    test = e == 0 ? r.e0_test : r.e1_test;
-                    tgt = e == 0 ? r.e0_tgt : r.e1_tgt;
-                } else {
-                    const uint2 ed = reinterpret_cast<const uint2 *>(a.edges)[r.edge_off + e];
-                    test = ed.x;
-                    tgt = ed.y;
-                }
-                if (!edge_matches(a, test, byte)) continue;
-                int lo = 0, hi = 1;
-                if (tgt & kTgtList) {
-                    const int idx = (int)(tgt & ~kTgtList);
-                    lo = a.cl_off[idx];
-                    hi = a.cl_off[idx + 1];
-                }
-                for (int t = lo; t < hi; ++t) {
-                    const uint32_t w = (tgt & kTgtList) ? a.cl[t] : tgt;
-                    const uint32_t q = w & kStateMask;
-                    const uint32_t bit = 1u << (q & 31);
-                    const uint32_t old = atomicOr(&bits[q >> 5], bit);
-                    if (!(old & bit)) nxt[atomicAdd(&sh[0], 1)] = w;
-                }
-            }
+        const int nN = frontier_step(a, cur, nF, c.xa[pos], nxt, bits, sh);
+        if (tid == 0 && pos >= pos0) {
+            ++c.T;
+            c.X += nN;
         }
-        __syncthreads();
-        const int nN = sh[0];
-        __syncthreads();
-        for (int j = tid; j < nN; j += NT) {
-            const uint32_t q = nxt[j] & kStateMask;
-            atomicAnd(&bits[q >> 5], ~(1u << (q & 31)));
-        }
-        if (tid == 0) {
-            sh[0] = 0;
-            if (pos >= pos0) {
-                ++c.T;
-                c.X += nN;
-            }
-        }
-        // labels of the final states, ascending, once each
-        int last = -1;
-        for (;;) {
-            int mine = 0x7fffffff;
-            for (int j = tid; j < nN; j += NT) {
-                if (!(nxt[j] & kTgtFinal)) continue;
-                const NfaRec r = a.rec[nxt[j] & kStateMask];
-                const int hi = r.lab_off + (int)(r.info >> 8);
-                for (int l = r.lab_off; l < hi; ++l) {
-                    const int v = a.lab[l];
-                    if (v > last) {
-                        mine = min(mine, v);
-                        break;
-                    }
-                }
-            }
-            const int m = block_min(mine, sh + 1);
-            if (m == 0x7fffffff) break;
+        frontier_labels(a, nxt, nN, sh, [&](int m) {
             if (tid == 0 && k >= k0) c.put(mode, s, pos, m, k, at);
             ++k;
-            last = m;
-        }
+        });
         uint32_t *t = cur;
         cur = nxt;
         nxt = t;
@@ -398,6 +437,10 @@ __device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0
         ++pos;
         __syncthreads();
     }
+    if (nF > 0 && mode != kWrite && a.carry.pairs)
+        for (int j = tid; j < nF; j += NT)
+            carry_write(a.carry, carry_reserve(a.carry, 1), s - c.dsh, cur[j] & kStateMask);
+    __syncthreads();
     return (long long)k - k0;
 }
 
@@ -447,6 +490,7 @@ __device__ __forceinline__ void drain_round(NfaCtx &c, Walk *q, int &qcount, Big
 #pragma unroll
     for (int j = 0; j < QK; ++j) {
         const bool keep = alive[j] && e[j].n > 0 && e[j].pos < c.n32;
+        if (alive[j] && e[j].n > 0 && e[j].pos >= c.n32) c.carry_set(e[j].start, e[j].s, e[j].n);
         const int slot = wave_push_slot(nc, keep);
         if (keep) q[slot] = e[j];
     }
@@ -519,6 +563,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     uint32_t *bits = a.big_bits + (size_t)b * ((ns + 31) / 32);
 
     NfaCtx c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf};
+    const bool cy = a.carry.pairs != nullptr;
     Walk *q = qall + wv * QW;
     uint32_t *lst = lst_all + wv * 512;
 
@@ -584,7 +629,9 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                     const bool pb = !a.pair_on || ((pbits_s[p >> 5] >> (p & 31)) & 1u);
                     const bool valid = (vmask >> k) & 1u;
                     const bool second = valid && n1 > 0 && i + 1 < n32;
-                    const bool take = valid && n1 > 0 && (e1 > 0 || (second && pb));
+                    // (with carries collected, the last start is listed too:
+                    // its first set is live at the end of the input)
+                    const bool take = valid && n1 > 0 && (e1 > 0 || (second && pb) || (cy && !second));
                     c.T += valid ? 1 : 0;
                     c.X += valid ? n1 : 0;
                     c.T += (second && !take) ? 1 : 0;
@@ -627,8 +674,12 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                                     ent.pos = i + 2;
                                     ent.k = km;
                                     ent.n = nS;
+                                } else if (nS > 0) {
+                                    c.carry_set(i, ent.s, nS);
                                 }
                             }
+                        } else {
+                            c.carry_first(i, c1);
                         }
                     }
                     while (qcount > QW - 64) drain_round(c, q, qcount, big_s, &nbig);
@@ -749,8 +800,64 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     finish_launch<NT>(a.ctl, a.lb, a.lb_cap, &last_s);
 }
 
+// Carried instances through a piece, one workgroup per instance: its state
+// set becomes the workgroup's frontier, which advances one byte at a time as
+// in a replay.  Count pass: matches per instance, and the instances still
+// live after the piece go to the carry list; write pass: the matches, in
+// (end, label) order, from the instance's output offset on.
+__global__ __launch_bounds__(NT) void nfa_resume_kernel(NfaResumeArgs r) {
+    __shared__ int sh[16];
+    const NfaArgs &a = r.a;
+    const int tid = threadIdx.x;
+    const size_t ns = (size_t)a.n_states;
+    uint32_t *F0 = a.big_front + (size_t)blockIdx.x * 2 * ns;
+    uint32_t *F1 = F0 + ns;
+    uint32_t *bits = a.big_bits + (size_t)blockIdx.x * ((ns + 31) / 32);
+    const int G = *r.in.n_groups;
+    if (tid == 0) sh[0] = 0;
+    __syncthreads();
+    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+        const int k0 = r.in.grp_off[g], k1 = r.in.grp_off[g + 1];
+        const int32_t start = (int32_t)(r.in.keys[k0] >> 32);
+        int nF = k1 - k0;
+        for (int j = tid; j < nF; j += NT) F0[j] = (uint32_t)r.in.keys[k0 + j];
+        __syncthreads();
+        const long long at = r.write ? r.off[g] : 0;
+        long long k = 0;  // tracked by every thread identically
+        uint32_t *cur = F0, *nxt = F1;
+        for (int64_t p = 0; p < a.n && nF > 0; ++p) {
+            const int nN = frontier_step(a, cur, nF, a.x[p], nxt, bits, sh);
+            frontier_labels(a, nxt, nN, sh, [&](int m) {
+                if (r.write && tid == 0 && at + k < a.cap) {
+                    MatchOut *o = &a.out[at + k];
+                    o->start = start;
+                    o->end = r.base + (int32_t)p;
+                    o->label = m;
+                }
+                ++k;
+            });
+            uint32_t *t = cur;
+            cur = nxt;
+            nxt = t;
+            nF = nN;
+            __syncthreads();
+        }
+        if (!r.write) {
+            if (tid == 0) r.cnt[g] = k;
+            for (int j = tid; j < nF; j += NT)
+                carry_write(a.carry, carry_reserve(a.carry, 1), start - a.carry.base, cur[j] & kStateMask);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 const void *nfa_kernel_fn() { return reinterpret_cast<const void *>(&nfa_scan_kernel); }
+
+hipError_t launch_nfa_resume(const NfaResumeArgs &r, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(nfa_resume_kernel, dim3(grid), dim3(NT), 0, s, r);
+    return hipGetLastError();
+}
 
 }  // namespace pfsmk

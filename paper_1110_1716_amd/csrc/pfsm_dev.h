@@ -57,6 +57,34 @@ struct MatchOut {
     int32_t start, end, label;
 };
 
+// Instances still live when a scan reaches the end of its input (chained
+// partitioning, Section III.D.3): each appends one (start, state) pair per
+// state it holds, start as a position of the whole stream (the piece's
+// first byte is `base`).  Pairs arrive in no particular order and may repeat;
+// *n counts every pair asked for, including those past cap.  Off when pairs
+// is null.
+struct CarryOut {
+    uint32_t *pairs;          // [2 * cap]
+    unsigned long long *n;
+    int64_t cap;
+    int32_t base;
+    int32_t pad;
+};
+
+__device__ __forceinline__ unsigned long long carry_reserve(const CarryOut &c, int cnt) {
+    return atomicAdd(c.n, (unsigned long long)cnt);
+}
+
+// Pair `slot` of a reservation: the instance started at `start` (a position
+// of the piece) holds `state`.
+__device__ __forceinline__ void carry_write(const CarryOut &c, unsigned long long slot, int32_t start,
+                                            uint32_t state) {
+    if (slot < (unsigned long long)c.cap) {
+        c.pairs[2 * slot] = (uint32_t)(c.base + start);
+        c.pairs[2 * slot + 1] = state;
+    }
+}
+
 // ---------------------------------------------------------------- DFA scan
 
 constexpr int kDfaThreads = 768;               // one workgroup, 12 wave64
@@ -110,6 +138,7 @@ struct DfaArgs {
     long long *bstats;          // [gridDim.x * 4] T, X, long walks, matches
     void *spill;                // [gridDim.x * kDfaSpill] walks parked out of LDS
     int64_t seg;                // bytes per segment (multiple of 16)
+    CarryOut carry;             // live instances at the end of the input
     // dynamic LDS layout, byte offsets
     int32_t off_flags, off_laboff, off_lab, off_tab, off_q, off_m, off_list, lds_bytes;
 };
@@ -191,6 +220,7 @@ struct NfaArgs {
     // bitset of n_states bits (all clear between uses)
     uint32_t *big_front;        // [gridDim.x * 2 * n_states]
     uint32_t *big_bits;         // [gridDim.x * ((n_states + 31) / 32)]
+    CarryOut carry;             // live instances at the end of the input
 };
 
 const void *nfa_kernel_fn();

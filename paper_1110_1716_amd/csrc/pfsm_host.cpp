@@ -18,6 +18,7 @@
 #include "host_common.h"
 #include "pfsm_dev.h"
 #include "pfsm_nfa.h"
+#include "stream.h"
 
 using namespace pfsmk;
 
@@ -61,6 +62,8 @@ struct pfsm {
     NfaPtr nfa;
     // ---- scan workspaces, one per stream
     WorkspacePool pool;
+    // ---- successful edits (streams opened before an edit refuse to go on)
+    uint64_t edits = 0;
 };
 
 namespace {
@@ -353,13 +356,19 @@ int pfsm_add_pattern(pfsm_t *h, const pfsm_nfa_desc *pattern, void *hip_stream) 
     if (!h || !pattern) return fail(PFSM_EINVAL, "NULL argument");
     if (h->kind == 0)
         return fail(PFSM_ENOSYS, "a DFA handle is one monolithic table; load the union as an NFA");
-    return nfa_add_pattern(h->nfa.get(), pattern, static_cast<hipStream_t>(hip_stream));
+    const int rc = nfa_add_pattern(h->nfa.get(), pattern, static_cast<hipStream_t>(hip_stream));
+    if (rc == PFSM_OK) ++h->edits;
+    return rc;
 }
 
 int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream) {
     if (!h) return fail(PFSM_EINVAL, "NULL handle");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (h->kind == 1) return nfa_remove_pattern(h->nfa.get(), label, s);
+    if (h->kind == 1) {
+        const int rc = nfa_remove_pattern(h->nfa.get(), label, s);
+        if (rc == PFSM_OK) ++h->edits;
+        return rc;
+    }
     if (has_label(h->disabled, label)) return fail(PFSM_ENOENT, "label %d already removed", label);
     bool found = false;
     for (auto &v : h->labels)
@@ -372,13 +381,15 @@ int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream) {
     // Scans already issued read the current caches: wait for the device,
     // then replace the caches.
     HIP_TRY(hipDeviceSynchronize());
+    ++h->edits;
     return dfa_upload_caches(h, s);
 }
 
 // One launch of the DFA scan kernel: a single stream (plan == nullptr) or the
 // segments of a batch plan.
 static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
-                      int64_t cap, int64_t *d_total, hipStream_t s) {
+                      int64_t cap, int64_t *d_total, hipStream_t s, const int64_t *d_base = nullptr,
+                      const CarryOut *carry = nullptr) {
     Workspace *w;
     int rc = h->pool.get(s, h->n_blocks, &w);
     if (rc) return rc;
@@ -419,8 +430,10 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
             return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)", (long long)n,
                         (long long)n_segs, w->lb_cap);
         a.n_segs = (int32_t)n_segs;
+        a.plan.base_dev = d_base;
         grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
     }
+    if (carry) a.carry = *carry;
     a.off_flags = h->off_flags;
     a.off_laboff = h->off_laboff;
     a.off_lab = h->off_lab;
@@ -749,3 +762,46 @@ void pfsm_free(pfsm_t *h) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- streams
+
+namespace pfsmk {
+
+uint64_t handle_edits(const pfsm_t *h) { return h->edits; }
+
+int piece_scan(pfsm_t *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap, int64_t *d_total,
+               const int64_t *d_base, const CarryOut *carry, hipStream_t s) {
+    if (h->kind == 1) return nfa_launch(h->nfa.get(), x, n, nullptr, 0, out, cap, d_total, s, d_base, carry);
+    return dfa_launch(h, x, n, nullptr, 0, out, cap, d_total, s, d_base, carry);
+}
+
+int piece_resume(pfsm_t *h, const uint8_t *x, int64_t n, int32_t base, const CarrySet &in, int64_t *cnt,
+                 const int64_t *off, MatchOut *out, int64_t cap, const CarryOut &carry, int write, hipStream_t s) {
+    if (h->kind == 1) return nfa_resume(h->nfa.get(), x, n, base, in, cnt, off, out, cap, carry, write, s);
+    DfaResumeArgs r;
+    std::memset(&r, 0, sizeof r);
+    r.x = x;
+    r.n = n;
+    r.base = base;
+    // the table as loaded (symbol columns through the byte map), not the
+    // byte-indexed resident image
+    r.tbl16 = h->tbl16 ? 1 : 0;
+    r.n_symbols = h->n_symbols;
+    r.identity = h->identity ? 1 : 0;
+    r.tbl = h->d_tbl.p;
+    r.b2s = h->d_b2s.as<int16_t>();
+    r.flags = h->d_flags.as<uint8_t>();
+    r.lab_off = h->d_lab_off.as<int32_t>();
+    r.lab = h->d_lab.as<int32_t>();
+    r.in = in;
+    r.cnt = cnt;
+    r.off = off;
+    r.out = out;
+    r.cap = cap;
+    r.carry = carry;
+    r.write = write;
+    HIP_TRY(launch_dfa_resume(r, s));
+    return PFSM_OK;
+}
+
+}  // namespace pfsmk

@@ -8,6 +8,7 @@
 #include "host_common.h"
 #include "pfsm.h"
 #include "pfsm_dev.h"
+#include "stream.h"
 
 namespace pfsmk {
 
@@ -24,8 +25,14 @@ int nfa_scan_async(NfaHost *h, const uint8_t *x, int64_t n, MatchOut *out, int64
                    hipStream_t s);
 // One launch of the scan kernel: a single stream (plan == nullptr) or the
 // segments of a batch plan.
+// d_base (single stream only): output index of the first match, on the
+// device; carry: collects the instances still live at the end of x.
 int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
-               int64_t cap, int64_t *d_total, hipStream_t s);
+               int64_t cap, int64_t *d_total, hipStream_t s, const int64_t *d_base = nullptr,
+               const CarryOut *carry = nullptr);
+// Count (write == 0) or write pass over carried instances (stream.h).
+int nfa_resume(NfaHost *h, const uint8_t *x, int64_t n, int32_t base, const CarrySet &in, int64_t *cnt,
+               const int64_t *off, MatchOut *out, int64_t cap, const CarryOut &carry, int write, hipStream_t s);
 int nfa_grid_blocks(NfaHost *h);
 WorkspacePool *nfa_pool(NfaHost *h);
 
