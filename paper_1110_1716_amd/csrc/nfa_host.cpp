@@ -364,7 +364,7 @@ int rebuild(NfaHost *h, hipStream_t s) {
 
 int grid_size(NfaHost *h) {
     int occ = 0, cus = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nfa_kernel_fn(), kNfaThreads, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nfa_kernel_fn(false), kNfaThreads, 0));
     int rc = device_cus(&cus);
     if (rc) return rc;
     if (occ < 1) return fail(PFSM_EINVAL, "NFA scan kernel does not fit on a compute unit");
@@ -530,7 +530,7 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
     }
     if (carry) a.carry = *carry;
     void *args[] = {&a};
-    HIP_TRY(hipLaunchKernel(nfa_kernel_fn(), dim3(grid), dim3(kNfaThreads), args, 0, s));
+    HIP_TRY(hipLaunchKernel(nfa_kernel_fn(carry != nullptr), dim3(grid), dim3(kNfaThreads), args, 0, s));
     w->last_grid = grid;
     w->scanned = true;
     return PFSM_OK;

@@ -53,7 +53,11 @@ struct Big {
 // Where a walk's matches go.
 enum Mode : int { kBuffer = 0, kCount = 1, kWrite = 2 };
 
+// kCarry: instances live at the end of the input are collected (streams);
+// plain scans compile those paths out.
+template <bool kCarry>
 struct NfaCtx {
+    static constexpr bool kCarryOn = kCarry;
     const NfaArgs &a;
     const uint32_t *pbits_s;
     const int32_t *f1o_s;
@@ -101,7 +105,7 @@ struct NfaCtx {
     // byte of the input: hand it to the next piece when carries are
     // collected.
     __device__ __forceinline__ void carry_set(int32_t start, const uint32_t (&S)[K], int n) const {
-        if (!a.carry.pairs) return;
+        if constexpr (!kCarry) return;
         const unsigned long long slot = carry_reserve(a.carry, n);
 #pragma unroll
         for (int j = 0; j < K; ++j)
@@ -109,7 +113,7 @@ struct NfaCtx {
     }
     // The same for the set after the first symbol c1 (start = the last byte).
     __device__ __forceinline__ void carry_first(int32_t start, int c1) const {
-        if (!a.carry.pairs) return;
+        if constexpr (!kCarry) return;
         const int lo = f1o_s[c1], hi = f1o_s[c1 + 1];
         const unsigned long long slot = carry_reserve(a.carry, hi - lo);
         for (int j = lo; j < hi; ++j) carry_write(a.carry, slot + (j - lo), start - dsh, a.f1[j] & kStateMask);
@@ -184,7 +188,8 @@ __device__ __forceinline__ bool nfa_step(const NfaArgs &a, const uint32_t (&S)[K
 }
 
 // Report the labels of the final states of O (ascending, once each).
-__device__ __forceinline__ void emit_set(NfaCtx &c, int mode, const uint32_t (&O)[K], int nO, int32_t start,
+template <class Ctx>
+__device__ __forceinline__ void emit_set(Ctx &c, int mode, const uint32_t (&O)[K], int nO, int32_t start,
                                          int32_t end, int32_t &k, int32_t k0, long long at) {
     bool any = false;
 #pragma unroll
@@ -216,7 +221,8 @@ __device__ __forceinline__ void emit_set(NfaCtx &c, int mode, const uint32_t (&O
 }
 
 // Report a sorted unique label list.
-__device__ __forceinline__ void emit_list(NfaCtx &c, int mode, const int32_t *lab, int lo, int hi, int32_t start,
+template <class Ctx>
+__device__ __forceinline__ void emit_list(Ctx &c, int mode, const int32_t *lab, int lo, int hi, int32_t start,
                                           int32_t end, int32_t &k, int32_t k0, long long at) {
     for (int l = lo; l < hi; ++l, ++k)
         if (k >= k0) c.put(mode, start, end, lab[l], k, at);
@@ -224,7 +230,8 @@ __device__ __forceinline__ void emit_list(NfaCtx &c, int mode, const int32_t *la
 
 // Sets after the first two symbols of start i (when i + 1 < n).  Returns the
 // number of states in the second set, or -1 when it exceeds K (S untouched).
-__device__ __forceinline__ int first_two(NfaCtx &c, int c1, int c2, uint32_t (&S)[K], int &pair_lab_lo,
+template <class Ctx>
+__device__ __forceinline__ int first_two(Ctx &c, int c1, int c2, uint32_t (&S)[K], int &pair_lab_lo,
                                          int &pair_lab_hi, bool &overflow) {
     const NfaArgs &a = c.a;
     overflow = false;
@@ -273,7 +280,8 @@ __device__ __forceinline__ int first_two(NfaCtx &c, int c1, int c2, uint32_t (&S
 // Full walk of one start by one lane, for the count and write passes of a
 // dense segment.  Returns the number of matches, or -1 when a set outgrows K
 // (the caller replays that start with the whole workgroup).
-__device__ __forceinline__ long long walk_lane(NfaCtx &c, int32_t i, int mode, long long at) {
+template <class Ctx>
+__device__ __forceinline__ long long walk_lane(Ctx &c, int32_t i, int mode, long long at) {
     const NfaArgs &a = c.a;
     int32_t k = 0;
     const int c1 = c.xa[i];
@@ -398,7 +406,8 @@ __device__ __forceinline__ void frontier_labels(const NfaArgs &a, const uint32_t
 // global scratch).  Matches before the k0-th are skipped (already reported);
 // work counters are kept for positions >= pos0 (earlier ones were counted).
 // Returns the number of matches reported from k0 on (every thread).
-__device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0, int32_t pos0, int mode, long long at,
+template <class Ctx>
+__device__ __forceinline__ long long walk_block(Ctx &c, int32_t s, int32_t k0, int32_t pos0, int mode, long long at,
                                 uint32_t *F0, uint32_t *F1, uint32_t *bits, int *sh) {
     // sh[0]: next frontier size, sh[1..NT/64]: reduction slots
     const NfaArgs &a = c.a;
@@ -437,7 +446,7 @@ __device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0
         ++pos;
         __syncthreads();
     }
-    if (nF > 0 && mode != kWrite && a.carry.pairs)
+    if (Ctx::kCarryOn && nF > 0 && mode != kWrite)
         for (int j = tid; j < nF; j += NT)
             carry_write(a.carry, carry_reserve(a.carry, 1), s - c.dsh, cur[j] & kStateMask);
     __syncthreads();
@@ -447,7 +456,8 @@ __device__ __forceinline__ long long walk_block(NfaCtx &c, int32_t s, int32_t k0
 // One queue round of this wave: every walk advances through the rest of the
 // 16-byte chunk holding its next position.  Walks whose set outgrows K go to
 // the workgroup's replay list.
-__device__ __forceinline__ void drain_round(NfaCtx &c, Walk *q, int &qcount, Big *big_s, int *nbig) {
+template <class Ctx>
+__device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *big_s, int *nbig) {
     const NfaArgs &a = c.a;
     const int lane = lane_id();
     Walk e[QK];
@@ -498,6 +508,7 @@ __device__ __forceinline__ void drain_round(NfaCtx &c, Walk *q, int &qcount, Big
     qcount = nc;
 }
 
+template <bool kCarry>
 __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     __shared__ uint32_t pbits_s[2048];
     __shared__ int32_t f1o_s[257];
@@ -562,8 +573,8 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     uint32_t *F1 = F0 + ns;
     uint32_t *bits = a.big_bits + (size_t)b * ((ns + 31) / 32);
 
-    NfaCtx c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf};
-    const bool cy = a.carry.pairs != nullptr;
+    NfaCtx<kCarry> c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf};
+    constexpr bool cy = kCarry;
     Walk *q = qall + wv * QW;
     uint32_t *lst = lst_all + wv * 512;
 
@@ -853,7 +864,10 @@ __global__ __launch_bounds__(NT) void nfa_resume_kernel(NfaResumeArgs r) {
 
 }  // namespace
 
-const void *nfa_kernel_fn() { return reinterpret_cast<const void *>(&nfa_scan_kernel); }
+const void *nfa_kernel_fn(bool carry) {
+    return carry ? reinterpret_cast<const void *>(&nfa_scan_kernel<true>)
+                 : reinterpret_cast<const void *>(&nfa_scan_kernel<false>);
+}
 
 hipError_t launch_nfa_resume(const NfaResumeArgs &r, int grid, hipStream_t s) {
     hipLaunchKernelGGL(nfa_resume_kernel, dim3(grid), dim3(NT), 0, s, r);

@@ -223,6 +223,8 @@ struct NfaArgs {
     CarryOut carry;             // live instances at the end of the input
 };
 
-const void *nfa_kernel_fn();
+// The scan kernel; `carry`: the variant that collects live instances at the
+// end of its input.
+const void *nfa_kernel_fn(bool carry);
 
 }  // namespace pfsmk
