@@ -206,6 +206,54 @@ int pfsm_scan_batch_async(pfsm_t *const *hs, int32_t n_automata, const uint8_t *
                           void *hip_stream);
 
 /* ---------------------------------------------------------------------
+ * Launch settings and the autotuner.  Settings change where and how the
+ * work runs, never the matches.  A handle's settings apply to its single
+ * scans, streams and batches; set them while no scan of the handle is in
+ * flight on another thread.
+ * --------------------------------------------------------------------- */
+enum {
+    PFSM_OPT_SEGMENT = 1,             /* bytes of input per segment: 0 = automatic (the input spread
+                                         over the resident workgroups, at most 64 KiB), otherwise a
+                                         multiple of 16 in [256, 65536]                            */
+    PFSM_OPT_WORKGROUPS_PER_CU = 2,   /* resident workgroups per compute unit: 0 = as many as fit   */
+    PFSM_OPT_TABLE_BUDGET = 3,        /* DFA: largest transition table kept in LDS, bytes; -1 =
+                                         default (96 KiB), 0 = always read the table through L2
+                                         (rows of q0's successors still cached in LDS)             */
+    PFSM_OPT_PAIR_CACHE = 4,          /* NFA: 1 = cache the sets after two symbols per byte pair
+                                         when they fit (default), 0 = never                        */
+    PFSM_OPT_MAX_WORKGROUPS_PER_CU = 5, /* read only: how many workgroups fit per compute unit      */
+    PFSM_OPT_RESIDENT_TABLE = 6       /* read only, DFA: 1 when the table is resident in LDS        */
+};
+
+/* Set a writable option (table budget and pair cache rebuild the device
+ * caches and synchronise the device).  Errors: PFSM_EINVAL (unknown option
+ * or value out of range), PFSM_ENOSYS (option of the other automaton kind),
+ * PFSM_ENOMEM, PFSM_EHIP.                                                 */
+int pfsm_set_option(pfsm_t *h, int32_t option, int64_t value, void *hip_stream);
+/* Read an option.  Errors: PFSM_EINVAL, PFSM_ENOSYS.                      */
+int pfsm_get_option(const pfsm_t *h, int32_t option, int64_t *value);
+
+/* What pfsm_tune kept: the settings (-1 for the cache option of the other
+ * kind), the time per scan of the sample before and after, the number of
+ * settings timed and the sample's match count.                           */
+typedef struct {
+    int64_t segment, workgroups_per_cu, table_budget, pair_cache;
+    double ms_before, ms_after;
+    int32_t configs, pad;
+    int64_t matches;
+} pfsm_tune_report;
+
+/* Autotune h on a sample of n device bytes: starting from the current
+ * settings, try the cache option (table budget or pair cache), then the
+ * workgroups per compute unit, then the segment size, each timed over
+ * `reps` scans, and keep each change that saves at least 2 %.  Every
+ * setting must reproduce the sample's match count, else PFSM_EINVAL (the
+ * settings are then unspecified).  Allocates its own output buffer;
+ * synchronises `hip_stream`.  Errors: PFSM_EINVAL, PFSM_ENOMEM, PFSM_EHIP. */
+int pfsm_tune(pfsm_t *h, const uint8_t *d_sample, int64_t n, int32_t reps, pfsm_tune_report *report,
+              void *hip_stream);
+
+/* ---------------------------------------------------------------------
  * Streaming scans: chained data partitioning (Section III.D.3).  A stream's
  * bytes are fed in pieces; every instance still live when a piece ends is
  * carried into the next one as its start and state set, so the matches of

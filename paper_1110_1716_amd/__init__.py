@@ -33,13 +33,21 @@ PFSM_ENOENT = -5
 PFSM_EEXIST = -6
 PFSM_ENOSYS = -7
 
+PFSM_OPT_SEGMENT = 1
+PFSM_OPT_WORKGROUPS_PER_CU = 2
+PFSM_OPT_TABLE_BUDGET = 3
+PFSM_OPT_PAIR_CACHE = 4
+PFSM_OPT_MAX_WORKGROUPS_PER_CU = 5
+PFSM_OPT_RESIDENT_TABLE = 6
+
 # Exported symbols of libpfsm.so, as declared in include/pfsm.h.
 EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pattern", "pfsm_scan",
            "pfsm_scan_async", "pfsm_scan_batch", "pfsm_scan_batch_async", "pfsm_last_stats", "pfsm_free",
            "pfsm_strerror", "pfsm_last_error", "pfsm_server_create", "pfsm_server_submit", "pfsm_server_submit_borrowed",
            "pfsm_server_wait",
            "pfsm_server_times", "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy",
-           "pfsm_stream_open", "pfsm_stream_feed", "pfsm_stream_info", "pfsm_stream_close")
+           "pfsm_stream_open", "pfsm_stream_feed", "pfsm_stream_info", "pfsm_stream_close",
+           "pfsm_set_option", "pfsm_get_option", "pfsm_tune")
 
 
 class PfsmError(RuntimeError):
@@ -64,6 +72,13 @@ class _NfaDesc(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("transitions", ctypes.c_int64), ("activations", ctypes.c_int64),
                 ("matches", ctypes.c_int64), ("long_walks", ctypes.c_int64)]
+
+
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("segment", ctypes.c_int64), ("workgroups_per_cu", ctypes.c_int64),
+                ("table_budget", ctypes.c_int64), ("pair_cache", ctypes.c_int64),
+                ("ms_before", ctypes.c_double), ("ms_after", ctypes.c_double),
+                ("configs", ctypes.c_int32), ("pad", ctypes.c_int32), ("matches", ctypes.c_int64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -110,6 +125,9 @@ def load_library(path: str = LIB_PATH):
         "pfsm_stream_feed": (ctypes.c_int, [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp]),
         "pfsm_stream_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]),
         "pfsm_stream_close": (None, [vp]),
+        "pfsm_set_option": (ctypes.c_int, [vp, i32, i64, vp]),
+        "pfsm_get_option": (ctypes.c_int, [vp, i32, ctypes.POINTER(i64)]),
+        "pfsm_tune": (ctypes.c_int, [vp, vp, i64, i32, ctypes.POINTER(_TuneReport), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -329,6 +347,26 @@ def pfsm_last_stats(h: Pfsm, stream=None) -> dict:
 
 def pfsm_free(h: Pfsm) -> None:
     h.free()
+
+
+def pfsm_set_option(h: Pfsm, option: int, value: int, stream=None) -> None:
+    _check(load_library().pfsm_set_option(h.ptr, int(option), int(value), _stream_ptr(stream)))
+
+
+def pfsm_get_option(h: Pfsm, option: int) -> int:
+    v = ctypes.c_int64()
+    _check(load_library().pfsm_get_option(h.ptr, int(option), ctypes.byref(v)))
+    return v.value
+
+
+def pfsm_tune(h: Pfsm, sample, reps: int = 10, stream=None) -> dict:
+    """Autotune h's launch settings on device bytes ``sample``; returns the
+    report (settings kept, ms per scan before and after, settings timed)."""
+    _check_input(sample)
+    r = _TuneReport()
+    _check(load_library().pfsm_tune(h.ptr, sample.data_ptr(), sample.numel(), int(reps), ctypes.byref(r),
+                                    _stream_ptr(stream)))
+    return {f: getattr(r, f) for f, _ in _TuneReport._fields_ if f != "pad"}
 
 
 class Stream:

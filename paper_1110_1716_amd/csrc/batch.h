@@ -40,6 +40,7 @@ struct BatchPlanArgs {
     int64_t *bases;             // [n_aut + 1] output index of each launch's first match
     int64_t *seg;               // [n_aut] bytes per segment of each launch
     int32_t blocks[kMaxBatchAutomata];  // resident workgroups of each launch's kernel
+    int32_t seg_fix[kMaxBatchAutomata]; // bytes per segment chosen for the automaton, 0 = adaptive
     int64_t *stream_lo, *stream_hi;  // [n_streams]
     BatchInfo *info;
     int32_t seg_cap, lb_cap;

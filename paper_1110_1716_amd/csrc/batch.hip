@@ -57,12 +57,14 @@ __global__ __launch_bounds__(PT) void batch_plan_kernel(BatchPlanArgs p) {
     }
     __syncthreads();
     // Segment size of each launch: its bytes over about twice its resident
-    // workgroups, within [seg_min, seg_max], a multiple of 16.
+    // workgroups, within [seg_min, seg_max], a multiple of 16 (or the size
+    // set for the automaton).
     if (tid < p.n_aut) {
         const long long want = 2ll * (p.blocks[tid] > 0 ? p.blocks[tid] : 1);
         long long sg = (bytes_s[tid] + want - 1) / want;
         sg = (sg + 15) / 16 * 16;
         sg = sg < p.seg_min ? p.seg_min : (sg > p.seg_max ? p.seg_max : sg);
+        if (p.seg_fix[tid] > 0) sg = p.seg_fix[tid];
         seg_s[tid] = sg;
         p.seg[tid] = sg;
     }

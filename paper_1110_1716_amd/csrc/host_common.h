@@ -97,6 +97,7 @@ struct Workspace {
     int64_t *h_total = nullptr;           // pinned
     long long *h_stats = nullptr;         // pinned [n_blocks * 4]
     bool scanned = false;
+    uint64_t used = 0;                    // launch sequence number of the last scan
     uint8_t *stage = nullptr;             // aligned copy of a misaligned input
     int64_t stage_cap = 0;
     uint32_t *big_front = nullptr;        // NFA replay frontiers
@@ -121,6 +122,14 @@ struct Workspace {
 struct WorkspacePool {
     std::mutex mu;
     std::vector<std::unique_ptr<Workspace>> ws;
+    uint64_t clock = 0;
+
+    // Record a launch in w (for find()).
+    void mark(Workspace *w) {
+        std::lock_guard<std::mutex> lk(mu);
+        w->scanned = true;
+        w->used = ++clock;
+    }
 
     // The workspace of `s`, created on first use for a grid of n_blocks.
     int get(hipStream_t s, int n_blocks, Workspace **out) {
@@ -151,11 +160,12 @@ struct WorkspacePool {
         return PFSM_OK;
     }
 
+    // The workspace of the most recent scan on `s` (grids of any size).
     Workspace *find(hipStream_t s) {
         std::lock_guard<std::mutex> lk(mu);
         Workspace *r = nullptr;
         for (auto &p : ws)
-            if (p->stream == s && p->scanned) r = p.get();
+            if (p->stream == s && p->scanned && (!r || p->used > r->used)) r = p.get();
         return r;
     }
 };
@@ -207,6 +217,21 @@ inline int workspace_stats(Workspace *w, long long v[4]) {
 
 // Compute units of the current device.
 int device_cus(int *out);
+
+// Tuning knobs of a handle (pfsm_set_option); 0 / -1 select the defaults.
+struct Knobs {
+    int64_t segment = 0;       // bytes per segment cap
+    int32_t wpc = 0;           // workgroups per compute unit
+    int64_t table_budget = -1; // DFA: largest LDS-resident table
+    int32_t pair_cache = 1;    // NFA: two-symbol cache allowed
+};
+
+// Resident workgroups of a launch: `wpc` per compute unit (at most the
+// occupancy limit `occ`; 0 = occ).
+inline int grid_blocks(int occ, int cus, int wpc) {
+    const int k = wpc > 0 && wpc < occ ? wpc : occ;
+    return k * cus;
+}
 
 // Split n bytes over a persistent grid of n_blocks workgroups: bytes per
 // workgroup and round (a multiple of 16) and the number of rounds.

@@ -57,6 +57,8 @@ struct NfaHost {
     std::vector<Part> parts;
     std::unique_ptr<NfaTables> tab;
     int n_blocks = 0;
+    int occ = 0, cus = 0;
+    Knobs knobs;
     WorkspacePool pool;
 };
 
@@ -308,8 +310,8 @@ int rebuild(NfaHost *h, hipStream_t s) {
     std::vector<uint32_t> p_bits(2048, 0);
     std::vector<int32_t> p_off(65537, 0), pl_off(65537, 0), p_lab;
     std::vector<uint32_t> p_st;
-    bool pair_on = true;
-    {
+    bool pair_on = h->knobs.pair_cache != 0;
+    if (pair_on) {
         std::vector<int32_t> s2;
         for (int c1 = 0; c1 < 256 && pair_on; ++c1) {
             for (int c2 = 0; c2 < 256; ++c2) {
@@ -368,7 +370,9 @@ int grid_size(NfaHost *h) {
     int rc = device_cus(&cus);
     if (rc) return rc;
     if (occ < 1) return fail(PFSM_EINVAL, "NFA scan kernel does not fit on a compute unit");
-    h->n_blocks = occ * cus;
+    h->occ = occ;
+    h->cus = cus;
+    h->n_blocks = grid_blocks(occ, cus, h->knobs.wpc);
     return PFSM_OK;
 }
 
@@ -417,6 +421,17 @@ int nfa_remove_pattern(NfaHost *h, int32_t label, hipStream_t s) {
 }
 
 int nfa_grid_blocks(NfaHost *h) { return h->n_blocks; }
+
+Knobs *nfa_knobs(NfaHost *h) { return &h->knobs; }
+
+int nfa_occupancy(NfaHost *h) { return h->occ; }
+
+int nfa_apply_knobs(NfaHost *h, bool tables, hipStream_t s) {
+    h->n_blocks = grid_blocks(h->occ, h->cus, h->knobs.wpc);
+    if (!tables) return PFSM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    return rebuild(h, s);
+}
 
 WorkspacePool *nfa_pool(NfaHost *h) { return &h->pool; }
 
@@ -508,8 +523,6 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
     a.cap = cap;
     a.total = d_total;
     a.ctl = w->ctl;
-    a.lb = w->lb;
-    a.lb_cap = w->lb_cap;
     a.bstats = w->bstats;
     a.big_front = w->big_front;
     a.big_bits = w->big_bits;
@@ -519,20 +532,21 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
         a.seg = seg;
     } else {
         int rounds;
-        plan_segments(n, h->n_blocks, kNfaSegMax, &a.seg, &rounds);
+        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kNfaSegMax, &a.seg, &rounds);
         const int64_t n_segs = (n + a.seg - 1) / a.seg;
-        if (n_segs > w->lb_cap)
-            return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)", (long long)n,
-                        (long long)n_segs, w->lb_cap);
+        if ((rc = grow_lb(w, (int)n_segs))) return rc;
         a.n_segs = (int32_t)n_segs;
         a.plan.base_dev = d_base;
         grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
     }
     if (carry) a.carry = *carry;
+    // after any growth of the look-back words above
+    a.lb = w->lb;
+    a.lb_cap = w->lb_cap;
     void *args[] = {&a};
     HIP_TRY(hipLaunchKernel(nfa_kernel_fn(carry != nullptr), dim3(grid), dim3(kNfaThreads), args, 0, s));
     w->last_grid = grid;
-    w->scanned = true;
+    h->pool.mark(w);
     return PFSM_OK;
 }
 

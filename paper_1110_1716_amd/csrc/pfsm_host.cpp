@@ -57,6 +57,8 @@ struct pfsm {
     int32_t off_flags = 0, off_laboff = 0, off_lab = 0, off_tab = 0, off_q = 0, off_m = 0, off_list = 0,
             lds_bytes = 0;
     int n_blocks = 0;
+    int occ = 0, cus = 0;  // workgroups per compute unit that fit; compute units
+    Knobs knobs;
     const void *kernel = nullptr;
     // ---- NFA
     NfaPtr nfa;
@@ -149,7 +151,8 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     // is expanded to bytes, so the kernel indexes the table by the byte.
     const int64_t ns_b = (int64_t)N * 256;
     const int64_t expanded_bytes = N <= 255 ? ns_b : ns_b + ns_b / 8;
-    const bool expand = !h->identity && N <= 256 && expanded_bytes <= kDfaTableBudget;
+    const int64_t budget = h->knobs.table_budget >= 0 ? h->knobs.table_budget : kDfaTableBudget;
+    const bool expand = !h->identity && N <= 256 && expanded_bytes <= budget;
     std::vector<int32_t> dexp;
     const int32_t *dl = h->delta.data();
     int32_t SD = S;
@@ -185,11 +188,11 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
         return off + kDfaWaves * kDfaList * 4;
     };
     const int64_t bytes8 = ns, bytes8d = ((ns + 3) & ~3ll) + (ns + 31) / 32 * 4, bytes16 = ns * 2;
-    if (N <= 255 && bytes8 <= kDfaTableBudget && lds_total(bytes8, true) <= kDfaLdsLimit) {
+    if (N <= 255 && bytes8 <= budget && lds_total(bytes8, true) <= kDfaLdsLimit) {
         enc = kEnc8;
         res.resize(ns);
         for (int64_t i = 0; i < ns; ++i) res[i] = dl[i] < 0 ? 255 : (uint8_t)dl[i];
-    } else if (N == 256 && bytes8d <= kDfaTableBudget && lds_total(bytes8d, true) <= kDfaLdsLimit) {
+    } else if (N == 256 && bytes8d <= budget && lds_total(bytes8d, true) <= kDfaLdsLimit) {
         enc = kEnc8D;
         const int64_t dead_off = (ns + 3) & ~3ll;
         res.assign(bytes8d, 0);
@@ -198,7 +201,7 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
             if (dl[i] < 0) dead[i >> 5] |= 1u << (i & 31);
             else res[i] = (uint8_t)dl[i];
         }
-    } else if (N <= 32767 && bytes16 <= kDfaTableBudget && lds_total(bytes16, true) <= kDfaLdsLimit) {
+    } else if (N <= 32767 && bytes16 <= budget && lds_total(bytes16, true) <= kDfaLdsLimit) {
         enc = kEnc16;
         res.resize(bytes16);
         int16_t *t = reinterpret_cast<int16_t *>(res.data());
@@ -268,7 +271,9 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, h->kernel, kDfaThreads, h->lds_bytes));
     if ((rc = device_cus(&cus))) return rc;
     if (occ < 1) return fail(PFSM_EINVAL, "DFA scan kernel does not fit on a compute unit");
-    h->n_blocks = occ * cus;
+    h->occ = occ;
+    h->cus = cus;
+    h->n_blocks = grid_blocks(occ, cus, h->knobs.wpc);
     return PFSM_OK;
 }
 
@@ -414,8 +419,6 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
     a.cap = cap;
     a.total = d_total;
     a.ctl = w->ctl;
-    a.lb = w->lb;
-    a.lb_cap = w->lb_cap;
     a.bstats = w->bstats;
     a.spill = w->spill;
     int grid = h->n_blocks;
@@ -424,16 +427,17 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
         a.seg = seg;
     } else {
         int rounds;
-        plan_segments(n, h->n_blocks, kDfaSegMax, &a.seg, &rounds);
+        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax, &a.seg, &rounds);
         const int64_t n_segs = (n + a.seg - 1) / a.seg;
-        if (n_segs > w->lb_cap)
-            return fail(PFSM_EINVAL, "input of %lld bytes needs %lld segments (at most %d)", (long long)n,
-                        (long long)n_segs, w->lb_cap);
+        if ((rc = grow_lb(w, (int)n_segs))) return rc;
         a.n_segs = (int32_t)n_segs;
         a.plan.base_dev = d_base;
         grid = (int)std::min<int64_t>(n_segs, h->n_blocks);
     }
     if (carry) a.carry = *carry;
+    // after any growth of the look-back words above
+    a.lb = w->lb;
+    a.lb_cap = w->lb_cap;
     a.off_flags = h->off_flags;
     a.off_laboff = h->off_laboff;
     a.off_lab = h->off_lab;
@@ -445,7 +449,7 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
     void *args[] = {&a};
     HIP_TRY(hipLaunchKernel(h->kernel, dim3(grid), dim3(kDfaThreads), args, h->lds_bytes, s));
     w->last_grid = grid;
-    w->scanned = true;
+    h->pool.mark(w);
     return PFSM_OK;
 }
 
@@ -483,6 +487,66 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
     if (*n_matches > cap)
         return fail(PFSM_EOVERFLOW, "%lld matches, capacity %lld", (long long)*n_matches, (long long)cap);
     return PFSM_OK;
+}
+
+int pfsm_set_option(pfsm_t *h, int32_t option, int64_t value, void *hip_stream) {
+    if (!h) return fail(PFSM_EINVAL, "NULL handle");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Knobs *k = h->kind == 1 ? nfa_knobs(h->nfa.get()) : &h->knobs;
+    switch (option) {
+    case PFSM_OPT_SEGMENT:
+        if (value != 0 && (value < 256 || value > 65536 || value % 16))
+            return fail(PFSM_EINVAL, "segment must be 0 or a multiple of 16 in [256, 65536]");
+        k->segment = value;
+        return PFSM_OK;
+    case PFSM_OPT_WORKGROUPS_PER_CU:
+        if (value < 0 || value > 64) return fail(PFSM_EINVAL, "workgroups per CU must be in [0, 64]");
+        k->wpc = (int32_t)value;
+        if (h->kind == 1) return nfa_apply_knobs(h->nfa.get(), false, s);
+        h->n_blocks = grid_blocks(h->occ, h->cus, k->wpc);
+        return PFSM_OK;
+    case PFSM_OPT_TABLE_BUDGET:
+        if (h->kind == 1) return fail(PFSM_ENOSYS, "the table budget applies to DFA handles");
+        if (value < -1 || value > kDfaLdsLimit) return fail(PFSM_EINVAL, "table budget must be in [-1, %d]", kDfaLdsLimit);
+        if (value == k->table_budget) return PFSM_OK;
+        k->table_budget = value;
+        HIP_TRY(hipDeviceSynchronize());  // scans in flight read the current caches
+        return dfa_upload_caches(h, s);
+    case PFSM_OPT_PAIR_CACHE:
+        if (h->kind == 0) return fail(PFSM_ENOSYS, "the pair cache applies to NFA handles");
+        if (value != 0 && value != 1) return fail(PFSM_EINVAL, "pair cache must be 0 or 1");
+        if (value == k->pair_cache) return PFSM_OK;
+        k->pair_cache = (int32_t)value;
+        return nfa_apply_knobs(h->nfa.get(), true, s);
+    default:
+        return fail(PFSM_EINVAL, "unknown option %d", option);
+    }
+}
+
+int pfsm_get_option(const pfsm_t *h, int32_t option, int64_t *value) {
+    if (!h || !value) return fail(PFSM_EINVAL, "NULL argument");
+    const Knobs *k = h->kind == 1 ? nfa_knobs(h->nfa.get()) : &h->knobs;
+    switch (option) {
+    case PFSM_OPT_SEGMENT: *value = k->segment; return PFSM_OK;
+    case PFSM_OPT_WORKGROUPS_PER_CU: *value = k->wpc; return PFSM_OK;
+    case PFSM_OPT_TABLE_BUDGET:
+        if (h->kind == 1) return fail(PFSM_ENOSYS, "the table budget applies to DFA handles");
+        *value = k->table_budget;
+        return PFSM_OK;
+    case PFSM_OPT_PAIR_CACHE:
+        if (h->kind == 0) return fail(PFSM_ENOSYS, "the pair cache applies to NFA handles");
+        *value = k->pair_cache;
+        return PFSM_OK;
+    case PFSM_OPT_MAX_WORKGROUPS_PER_CU:
+        *value = h->kind == 1 ? nfa_occupancy(h->nfa.get()) : h->occ;
+        return PFSM_OK;
+    case PFSM_OPT_RESIDENT_TABLE:
+        if (h->kind == 1) return fail(PFSM_ENOSYS, "the table encoding applies to DFA handles");
+        *value = (h->enc == kEnc8 || h->enc == kEnc8D || h->enc == kEnc16) ? 1 : 0;
+        return PFSM_OK;
+    default:
+        return fail(PFSM_EINVAL, "unknown option %d", option);
+    }
 }
 
 }  // extern "C"
@@ -599,8 +663,10 @@ static int batch_enqueue(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d
     p.seg_max = kBatchSegMax;
     p.max_stream = kMaxStream;
     p.seg = bw->seg;
-    for (int a = 0; a < n_automata; ++a)
+    for (int a = 0; a < n_automata; ++a) {
         p.blocks[a] = hs[a]->kind == 1 ? nfa_grid_blocks(hs[a]->nfa.get()) : hs[a]->n_blocks;
+        p.seg_fix[a] = (int32_t)(hs[a]->kind == 1 ? nfa_knobs(hs[a]->nfa.get())->segment : hs[a]->knobs.segment);
+    }
     p.seg_first = bw->seg_first;
     p.seg_stream = bw->seg_stream;
     p.n_segs = bw->n_segs;

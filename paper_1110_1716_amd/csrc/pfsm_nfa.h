@@ -34,6 +34,10 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
 int nfa_resume(NfaHost *h, const uint8_t *x, int64_t n, int32_t base, const CarrySet &in, int64_t *cnt,
                const int64_t *off, MatchOut *out, int64_t cap, const CarryOut &carry, int write, hipStream_t s);
 int nfa_grid_blocks(NfaHost *h);
+Knobs *nfa_knobs(NfaHost *h);
+int nfa_occupancy(NfaHost *h);
+// After a change of h's knobs: the grid, and the tables when `tables`.
+int nfa_apply_knobs(NfaHost *h, bool tables, hipStream_t s);
 WorkspacePool *nfa_pool(NfaHost *h);
 
 }  // namespace pfsmk
