@@ -17,7 +17,8 @@
 //      coordinates;
 //   6. after one synchronisation (the match total and the pair count): the
 //      carry pairs become sorted unique keys grouped by start, the carried
-//      set of the next piece.
+//      set of the next piece (one workgroup sorts a few thousand pairs in
+//      LDS; more go through a device-wide radix sort).
 // The stream state changes only when a piece succeeds, so a piece refused
 // for lack of output room can be fed again with a larger buffer.
 #include <hipcub/hipcub.hpp>
@@ -106,6 +107,58 @@ __global__ __launch_bounds__(ST) void compact_kernel(const unsigned long long *s
     }
 }
 
+// Sort, deduplicate and group at most kSmallCarry pairs in one workgroup
+// (bitonic sort of the keys in LDS), for the usual case of a few carried
+// instances: one launch instead of a device-wide sort.
+constexpr int kSmallCarry = 2048;
+
+__global__ __launch_bounds__(ST) void small_carry_kernel(const uint32_t *pairs, int m, unsigned long long *keys,
+                                                         int32_t *grp_off, int32_t *n_groups) {
+    __shared__ unsigned long long k_s[kSmallCarry];
+    __shared__ long long red[ST / 64];
+    const int tid = threadIdx.x;
+    int np = 1;
+    while (np < m) np <<= 1;
+    for (int i = tid; i < np; i += ST)
+        k_s[i] = i < m ? ((unsigned long long)pairs[2 * i] << 32) | pairs[2 * i + 1] : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < np; i += ST) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = k_s[i], b = k_s[j];
+                    if ((a > b) == up) {
+                        k_s[i] = b;
+                        k_s[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    long long run_u = 0, run_g = 0;
+    for (int c0 = 0; c0 < m; c0 += ST) {
+        const int i = c0 + tid;
+        const bool in = i < m;
+        const unsigned long long k = in ? k_s[i] : 0;
+        const unsigned long long prev = in && i > 0 ? k_s[i - 1] : 0;
+        const bool uniq = in && (i == 0 || k != prev);
+        const bool head = in && (i == 0 || (k >> 32) != (prev >> 32));
+        long long tot_u, tot_g;
+        const long long ex_u = block_excl_scan<ST>(uniq ? 1 : 0, red, &tot_u);
+        const long long ex_g = block_excl_scan<ST>(head ? 1 : 0, red, &tot_g);
+        if (uniq) keys[run_u + ex_u] = k;
+        if (head) grp_off[run_g + ex_g] = (int32_t)(run_u + ex_u);
+        run_u += tot_u;
+        run_g += tot_g;
+    }
+    if (tid == 0) {
+        grp_off[run_g] = (int32_t)run_u;
+        *n_groups = (int32_t)run_g;
+    }
+}
+
 template <typename T>
 int grow_dev(T **p, int64_t *cap, int64_t need, hipStream_t s) {
     if (need <= *cap) return PFSM_OK;
@@ -140,22 +193,22 @@ struct pfsm_stream {
     // per-piece buffers
     uint32_t *pairs = nullptr;
     int64_t c_pairs = 0;
-    unsigned long long *n_pairs = nullptr;
+    int64_t *d_back = nullptr;  // [2]: match total, carry pairs asked for (read back together)
     unsigned long long *sort_in = nullptr, *sort_out = nullptr;
     int64_t c_sort_in = 0, c_sort_out = 0;
     void *sort_tmp = nullptr;
     size_t c_sort_tmp = 0;
     int64_t *cnt = nullptr, *off = nullptr;
     int64_t c_cnt = 0, c_off = 0;
-    int64_t *d_r = nullptr, *d_total = nullptr;
-    int64_t *h_back = nullptr;  // pinned: total, pairs asked for
+    int64_t *d_r = nullptr;
+    int64_t *h_back = nullptr;  // pinned mirror of d_back
 
     ~pfsm_stream() {
         for (int i = 0; i < 2; ++i) {
             if (keys[i]) (void)hipFree(keys[i]);
             if (grp[i]) (void)hipFree(grp[i]);
         }
-        void *dev[] = {n_groups, pairs, n_pairs, sort_in, sort_out, sort_tmp, cnt, off, d_r, d_total};
+        void *dev[] = {n_groups, pairs, d_back, sort_in, sort_out, sort_tmp, cnt, off, d_r};
         for (void *p : dev)
             if (p) (void)hipFree(p);
         if (h_back) (void)hipHostFree(h_back);
@@ -177,8 +230,8 @@ int pfsm_stream_open(pfsm_stream_t **out, pfsm_t *h) {
         return e != hipSuccess;
     };
     if (bad(hipGetDevice(&st->device)) || bad(hipMalloc(&st->n_groups, 2 * sizeof(int32_t))) ||
-        bad(hipMemset(st->n_groups, 0, 2 * sizeof(int32_t))) || bad(hipMalloc(&st->n_pairs, sizeof(unsigned long long))) ||
-        bad(hipMalloc(&st->d_r, sizeof(int64_t))) || bad(hipMalloc(&st->d_total, sizeof(int64_t))) ||
+        bad(hipMemset(st->n_groups, 0, 2 * sizeof(int32_t))) || bad(hipMalloc(&st->d_back, 2 * sizeof(int64_t))) ||
+        bad(hipMalloc(&st->d_r, sizeof(int64_t))) ||
         bad(hipHostMalloc(&st->h_back, 2 * sizeof(int64_t), hipHostMallocDefault)) ||
         bad(hipDeviceSynchronize())) {
         delete st;
@@ -214,23 +267,23 @@ int pfsm_stream_feed(pfsm_stream_t *st, const uint8_t *d_piece, int64_t n, pfsm_
         (rc = grow_dev(&st->pairs, &st->c_pairs, 1024, s)))
         return rc;
     for (;;) {
-        const CarryOut co{st->pairs, st->n_pairs, st->c_pairs / 2, base, 0};
-        hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(1), 0, s, st->n_pairs, st->d_r);
+        unsigned long long *n_pairs = reinterpret_cast<unsigned long long *>(st->d_back + 1);
+        const CarryOut co{st->pairs, n_pairs, st->c_pairs / 2, base, 0};
+        hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(1), 0, s, n_pairs, st->d_r);
         HIP_TRY(hipGetLastError());
         if (st->bound > 0) {
             if ((rc = piece_resume(st->h, d_piece, n, base, in, st->cnt, nullptr, nullptr, 0, co, 0, s))) return rc;
             hipLaunchKernelGGL(count_scan_kernel, dim3(1), dim3(ST), 0, s, st->cnt, in.n_groups, st->off, st->d_r);
             HIP_TRY(hipGetLastError());
         }
-        if ((rc = piece_scan(st->h, d_piece, n, out, cap, st->d_total, st->d_r, &co, s))) return rc;
+        if ((rc = piece_scan(st->h, d_piece, n, out, cap, st->d_back, st->d_r, &co, s))) return rc;
         if (st->bound > 0 && cap > 0)
             if ((rc = piece_resume(st->h, d_piece, n, base, in, nullptr, st->off, out, cap, co, 1, s))) return rc;
         if (cap > 0) {
-            hipLaunchKernelGGL(shift_kernel, dim3(256), dim3(256), 0, s, out, st->d_r, st->d_total, cap, base);
+            hipLaunchKernelGGL(shift_kernel, dim3(256), dim3(256), 0, s, out, st->d_r, st->d_back, cap, base);
             HIP_TRY(hipGetLastError());
         }
-        HIP_TRY(hipMemcpyAsync(st->h_back, st->d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(st->h_back + 1, st->n_pairs, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(st->h_back, st->d_back, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const int64_t want = st->h_back[1];
         if (want <= st->c_pairs / 2) break;
@@ -246,10 +299,16 @@ int pfsm_stream_feed(pfsm_stream_t *st, const uint8_t *d_piece, int64_t n, pfsm_
     // The pairs become the next piece's carried set.
     const int nx = 1 - cur;
     if ((rc = grow_dev(&st->keys[nx], &st->c_keys[nx], m, s)) ||
-        (rc = grow_dev(&st->grp[nx], &st->c_grp[nx], m + 1, s)) ||
-        (rc = grow_dev(&st->sort_in, &st->c_sort_in, m, s)) || (rc = grow_dev(&st->sort_out, &st->c_sort_out, m, s)))
+        (rc = grow_dev(&st->grp[nx], &st->c_grp[nx], m + 1, s)))
         return rc;
-    if (m > 0) {
+    if (m > kSmallCarry &&
+        ((rc = grow_dev(&st->sort_in, &st->c_sort_in, m, s)) || (rc = grow_dev(&st->sort_out, &st->c_sort_out, m, s))))
+        return rc;
+    if (m <= kSmallCarry) {
+        hipLaunchKernelGGL(small_carry_kernel, dim3(1), dim3(ST), 0, s, st->pairs, (int)m, st->keys[nx], st->grp[nx],
+                           st->n_groups + nx);
+        HIP_TRY(hipGetLastError());
+    } else {
         hipLaunchKernelGGL(keys_kernel, dim3(256), dim3(256), 0, s, st->pairs, m, st->sort_in);
         HIP_TRY(hipGetLastError());
         size_t need = 0;
@@ -264,10 +323,10 @@ int pfsm_stream_feed(pfsm_stream_t *st, const uint8_t *d_piece, int64_t n, pfsm_
         }
         size_t have = st->c_sort_tmp;
         HIP_TRY(hipcub::DeviceRadixSort::SortKeys(st->sort_tmp, have, st->sort_in, st->sort_out, (int)m, 0, 64, s));
+        hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(ST), 0, s, st->sort_out, m, st->keys[nx], st->grp[nx],
+                           st->n_groups + nx);
+        HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(ST), 0, s, st->sort_out, m, st->keys[nx], st->grp[nx],
-                       st->n_groups + nx);
-    HIP_TRY(hipGetLastError());
     st->cur = nx;
     st->bound = m;
     st->position += n;

@@ -113,6 +113,15 @@ def test_sigma_plus_every_start_carried(P):
     assert len(ref) == n * (n + 1) // 2
 
 
+def test_sigma_plus_many_carried(P):
+    # more carried instances than one workgroup sorts in LDS: the
+    # device-wide sort path
+    n = 4000
+    x = np.random.default_rng(17).integers(0, 256, n, dtype=np.uint8)
+    ref = check_stream(P, W.sigma_plus_dfa(), x, [2500, 2501, 3999], carried=lambda k: k)
+    assert len(ref) == n * (n + 1) // 2
+
+
 def test_sigma_plus_nfa_every_start_carried(P):
     n = 700
     x = np.random.default_rng(15).integers(0, 256, n, dtype=np.uint8)
