@@ -324,12 +324,15 @@ __device__ __forceinline__ bool advance_staged(DfaCtx<ENC, kId> &c, bool act, in
 
 // The full walk of one start reading the input through the cache hierarchy;
 // counts its matches, or writes them from output index `at` when write.
+// With `work`, adds its instance-steps and live steps to work[0] and work[1].
 template <int ENC, bool kId>
-__device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32_t i, bool write, long long at) {
+__device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32_t i, bool write, long long at,
+                                                long long *work = nullptr) {
     const DfaArgs &a = c.a;
-    long long cnt = 0;
+    long long cnt = 0, nT = 1, nX = 0;
     int s = c.first_state(c.xa[i]);
     int32_t pos = i;
+    if (s >= 0) nX = 1;
     while (s >= 0) {
         for (int l = c.lab_lo(s); l < c.lab_lo(s + 1); ++l, ++cnt) {
             if (write && at + cnt < a.cap) {
@@ -345,6 +348,12 @@ __device__ __forceinline__ long long walk_start(const DfaCtx<ENC, kId> &c, int32
         }
         const int sy = c.sym(c.xa[pos]);
         s = sy < 0 ? -1 : c.live(c.tab(s, sy));
+        ++nT;
+        nX += s >= 0 ? 1 : 0;
+    }
+    if (work) {
+        work[0] += nT;
+        work[1] += nX;
     }
     return cnt;
 }
@@ -487,7 +496,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         c.seg_lo = own_lo;
         c.sl = sl;
         c.sl32 = (int32_t)sl;
-        const long long m_before = c.M;
+        const long long m_before = c.M, t_before = c.T, x_before = c.X;
         if (sl < sh) *reinterpret_cast<uint4 *>(ring + 16 * lane) = cur;
 
         for (int64_t wb = sl; wb < sh; wb += WIN) {
@@ -587,8 +596,21 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             while (qcount > 0) drain_round<false>(c, q, qcount);
         }
 
+        __syncthreads();
+        long long seg_m = c.M - m_before;
+        if (ovf) {
+            // Walks were dropped (or matches did not fit): the segment's
+            // count and work come from a fresh walk of every owned start.
+            long long work[2] = {0, 0};
+            seg_m = 0;
+            for (int64_t i = own_lo + tid; i < own_hi; i += NT) seg_m += walk_start(c, (int32_t)i, false, 0, work);
+            c.T = t_before + work[0];
+            c.X = x_before + work[1];
+            c.M = m_before + seg_m;
+        }
+
         // The segment's count, its offset by look-back, and placement.
-        const long long mine_m = block_sum<NT>(c.M - m_before, red);
+        const long long mine_m = block_sum<NT>(seg_m, red);
         if (tid == 0) seg_s = take_ticket(a.ctl);  // the next segment, requested early
         if (wv == 0) {
             const long long ex = lookback(a.lb, sg, epoch, mine_m);

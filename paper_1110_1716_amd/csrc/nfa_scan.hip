@@ -279,17 +279,27 @@ __device__ __forceinline__ int first_two(Ctx &c, int c1, int c2, uint32_t (&S)[K
 //
 // Full walk of one start by one lane, for the count and write passes of a
 // dense segment.  Returns the number of matches, or -1 when a set outgrows K
-// (the caller replays that start with the whole workgroup).
+// (the caller replays that start with the whole workgroup).  With `work`,
+// its instance-steps and state activations are added to c.T and c.X (only
+// when the walk completes).
 template <class Ctx>
-__device__ __forceinline__ long long walk_lane(Ctx &c, int32_t i, int mode, long long at) {
+__device__ __forceinline__ long long walk_lane(Ctx &c, int32_t i, int mode, long long at, bool work = false) {
     const NfaArgs &a = c.a;
     int32_t k = 0;
     const int c1 = c.xa[i];
     const int n1 = c.f1o_s[c1 + 1] - c.f1o_s[c1];
-    if (n1 == 0) return 0;
+    long long nT = 1, nX = n1;
+    if (n1 == 0) {
+        if (work) ++c.T;
+        return 0;
+    }
     emit_list(c, mode, a.e1, c.e1o_s[c1], c.e1o_s[c1 + 1], i, i, k, 0, at);
     if (i + 1 >= c.n32) {
         if (mode == kCount) c.carry_first(i, c1);
+        if (work) {
+            c.T += nT;
+            c.X += nX;
+        }
         return k;
     }
     uint32_t S[K];
@@ -299,11 +309,15 @@ __device__ __forceinline__ long long walk_lane(Ctx &c, int32_t i, int mode, long
     if (ovf) return -1;
     if (a.pair_on) emit_list(c, mode, a.p_lab, llo, lhi, i, i + 1, k, 0, at);
     else emit_set(c, mode, S, nS, i, i + 1, k, 0, at);
+    ++nT;
+    nX += nS;
     int32_t pos = i + 2;
     while (nS > 0 && pos < c.n32) {
         uint32_t O[K];
         int nO;
         if (!nfa_step(a, S, nS, c.xa[pos], O, nO)) return -1;
+        ++nT;
+        nX += nO;
         emit_set(c, mode, O, nO, i, pos, k, 0, at);
 #pragma unroll
         for (int j = 0; j < K; ++j) S[j] = O[j];
@@ -311,6 +325,10 @@ __device__ __forceinline__ long long walk_lane(Ctx &c, int32_t i, int mode, long
         ++pos;
     }
     if (nS > 0 && mode == kCount) c.carry_set(i, S, nS);
+    if (work) {
+        c.T += nT;
+        c.X += nX;
+    }
     return k;
 }
 
@@ -609,7 +627,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         const int32_t n32 = c.n32;
         const int64_t own_lo = seg_lo + dsh, own_hi = seg_hi + dsh;
         c.seg_lo = own_lo;
-        const long long m_before = c.M;
+        const long long m_before = c.M, t_before = c.T, x_before = c.X;
         int qcount = 0;
         for (int64_t wbase = own_lo & ~(int64_t)15; wbase < own_hi; wbase += W) {
             const int64_t i0 = wbase + 16 * tid;
@@ -717,9 +735,32 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         }
         __syncthreads();
         if (!ovf) run_big();
+        __syncthreads();
+        long long seg_m = c.M - m_before;
+        if (ovf) {
+            // Starts were dropped from the replay list (or matches did not
+            // fit): the segment's count and work come from fresh walks of
+            // every owned start.
+            c.T = t_before;
+            c.X = x_before;
+            seg_m = 0;
+            for (int64_t c0 = own_lo; c0 < own_hi; c0 += NT) {
+                const int64_t i = c0 + tid;
+                long long cnt = i < own_hi ? walk_lane(c, (int32_t)i, kCount, 0, true) : 0;
+                for (;;) {
+                    const int want = block_min(cnt < 0 ? tid : 0x7fffffff, sh + 1);
+                    if (want == 0x7fffffff) break;
+                    const long long v = walk_block(c, (int32_t)(c0 + want), 0, 0, kCount, 0, F0, F1, bits, sh);
+                    if (tid == want) cnt = v;
+                    __syncthreads();
+                }
+                seg_m += cnt;
+            }
+            c.M = m_before + seg_m;
+        }
 
         // The segment's count, its offset by look-back, and placement.
-        const long long mine_m = block_sum<NT>(c.M - m_before, red);
+        const long long mine_m = block_sum<NT>(seg_m, red);
         if (tid == 0) seg_s = take_ticket(a.ctl);  // the next segment, requested early
         if (wv == 0) {
             const long long ex = lookback(a.lb, sg, epoch, mine_m);

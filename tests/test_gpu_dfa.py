@@ -180,3 +180,20 @@ def test_invalid_descriptors_rejected(P):
     bad2 = W.DFA(d.n_states, 200, d.q0, None, d.delta[:200 * d.n_states], d.final_off, d.final_labels)
     with pytest.raises(P.PfsmError):
         P.pfsm_load(bad2)
+
+
+def test_dropped_walks_recounted(P):
+    # every start lives to the end of its line: with 64 KiB segments the
+    # parked walks outgrow the spill area, the segment falls back to fresh
+    # per-start walks, and its count and work must still be exact
+    wl = W.log_search(n=256 << 10, line_mean=512)
+    ref, wk = oracle.scan(wl.automaton, wl.data)
+    h = P.pfsm_load(wl.automaton)
+    try:
+        P.pfsm_set_option(h, P.PFSM_OPT_SEGMENT, 65536)
+        n, out = P.pfsm_scan(h, dev(wl.data))
+        assert np.array_equal(out.cpu().numpy(), ref)
+        st = P.pfsm_last_stats(h)
+        assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
+    finally:
+        h.free()

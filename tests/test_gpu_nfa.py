@@ -181,3 +181,24 @@ def test_back_to_back_async(P):
         c = int(cnts[i].item())
         assert c == len(ref) and np.array_equal(outs[i][:c].cpu().numpy(), ref)
     h.free()
+
+
+def test_replay_list_overflow_recounted(P):
+    # sets larger than a lane keeps at every start: more replays than the
+    # list holds, so the segment falls back to fresh per-start walks
+    pats = [(b"[a-d]*a", 0), (b"[a-d]*b", 1), (b"[a-d]*c[a-d]", 2), (b"[ab]*dd", 3), (b"(a|c)*b[a-d]", 4),
+            (b"[a-d]*ab", 5), (b"[cd]*a", 6)]
+    fsm = regex_nfa(pats)
+    rng = np.random.default_rng(41)
+    x = rng.choice(list(b"abcd"), 16384).astype(np.uint8)
+    x[rng.random(x.size) < 0.02] = ord("e")  # walks end at an 'e'
+    ref, wk = oracle.scan(fsm, x)
+    h = P.pfsm_load(fsm)
+    try:
+        P.pfsm_set_option(h, P.PFSM_OPT_SEGMENT, 4096)
+        n, out = P.pfsm_scan(h, dev(x))
+        assert np.array_equal(out.cpu().numpy(), ref)
+        st = P.pfsm_last_stats(h)
+        assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
+    finally:
+        h.free()

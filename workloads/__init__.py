@@ -184,6 +184,25 @@ def literal_dfa(pattern: bytes, label: int = 0) -> DFA:
     return DFA(m + 1, 256, 0, None, delta, off, lab)
 
 
+def kmp_dfa(pattern: bytes, kill: bytes = b"\n", label: int = 0) -> DFA:
+    """Search DFA for ``[^kill]*pattern`` over bytes (the Knuth-Morris-Pratt
+    automaton: state q = the longest prefix of the pattern that ends here);
+    a kill byte has no transition, so an instance lives until the next one."""
+    m = len(pattern)
+    delta = np.zeros((m + 1, 256), dtype=np.int32)
+    delta[0, pattern[0]] = 1
+    back = 0
+    for q in range(1, m + 1):
+        delta[q] = delta[back]
+        if q < m:
+            delta[q, pattern[q]] = q + 1
+            back = int(delta[back, pattern[q]])
+    for k in kill:
+        delta[:, k] = -1
+    off, lab = label_csr(m + 1, {m: [label]})
+    return DFA(m + 1, 256, 0, None, delta.ravel(), off, lab)
+
+
 # --------------------------------------------------------------------------
 # Random small automata for property tests
 # --------------------------------------------------------------------------
@@ -453,6 +472,25 @@ def cfg3(seed: int = 3, n: int = 64 * MiB, n_patterns: int = 2000, plant_rate: f
             plants.append((off, w.size, sig.label))
     return Workload(f"NFA union of {n_patterns} signature chains, {n >> 20} MiB Zipf(1.1) bytes",
                     nfa, x, seed, {"plants": plants, "signatures": sigs, "perm": perm})
+
+
+def log_search(seed: int = 6, n: int = 16 * MiB, line_mean: int = 1024, pattern: bytes = b"ERROR",
+               hits_per_line: float = 0.5) -> Workload:
+    """Long walks: the ``[^\n]*ERROR`` search DFA over text lines.  Bytes are
+    lowercase letters and spaces, each byte a newline with probability
+    1/line_mean; the pattern is written at uniform positions, about
+    hits_per_line times per line.  Every start stays live until the end of
+    its line, so a per-start walk averages about line_mean/2 steps."""
+    rng = rng_for(seed)
+    alpha = np.frombuffer(b"abcdefghijklmnopqrstuvwxyz ", np.uint8)
+    x = alpha[rng.integers(0, alpha.size, n)]
+    x[rng.random(n) < 1.0 / line_mean] = ord("\n")
+    k = int(n / line_mean * hits_per_line)
+    pat = np.frombuffer(pattern, np.uint8)
+    for off in rng.integers(0, max(1, n - pat.size), k):
+        x[off:off + pat.size] = pat
+    return Workload(f"log search [^\\n]*{pattern.decode()}, lines ~{line_mean} B, {n} B", kmp_dfa(pattern), x, seed,
+                    {"line_mean": line_mean})
 
 
 @dataclass
