@@ -222,7 +222,11 @@ enum {
     PFSM_OPT_PAIR_CACHE = 4,          /* NFA: 1 = cache the sets after two symbols per byte pair
                                          when they fit (default), 0 = never                        */
     PFSM_OPT_MAX_WORKGROUPS_PER_CU = 5, /* read only: how many workgroups fit per compute unit      */
-    PFSM_OPT_RESIDENT_TABLE = 6       /* read only, DFA: 1 when the table is resident in LDS        */
+    PFSM_OPT_RESIDENT_TABLE = 6,      /* read only, DFA: 1 when the table is resident in LDS        */
+    PFSM_OPT_MERGED_WALKS = 7         /* DFA with at most 63 states: 1 = tag-merged stepping (one
+                                         lookup per distinct active state, Section III.B) for single
+                                         scans; 0 = one walk per start (default).  Batches and
+                                         streams always walk per start.                            */
 };
 
 /* Set a writable option (table budget and pair cache rebuild the device
@@ -234,18 +238,20 @@ int pfsm_set_option(pfsm_t *h, int32_t option, int64_t value, void *hip_stream);
 int pfsm_get_option(const pfsm_t *h, int32_t option, int64_t *value);
 
 /* What pfsm_tune kept: the settings (-1 for the cache option of the other
- * kind), the time per scan of the sample before and after, the number of
- * settings timed and the sample's match count.                           */
+ * kind; merged_walks is 0 for NFAs), the time per scan of the sample before
+ * and after, the number of settings timed and the sample's match count.   */
 typedef struct {
     int64_t segment, workgroups_per_cu, table_budget, pair_cache;
     double ms_before, ms_after;
     int32_t configs, pad;
     int64_t matches;
+    int64_t merged_walks;
 } pfsm_tune_report;
 
 /* Autotune h on a sample of n device bytes: starting from the current
- * settings, try the cache option (table budget or pair cache), then the
- * workgroups per compute unit, then the segment size, each timed over
+ * settings, try tag-merged stepping (DFAs that allow it), the cache option
+ * (table budget or pair cache), then the workgroups per compute unit, then
+ * the segment size, each timed over
  * `reps` scans, and keep each change that saves at least 2 %.  Every
  * setting must reproduce the sample's match count, else PFSM_EINVAL (the
  * settings are then unspecified).  Allocates its own output buffer;

@@ -39,6 +39,7 @@ PFSM_OPT_TABLE_BUDGET = 3
 PFSM_OPT_PAIR_CACHE = 4
 PFSM_OPT_MAX_WORKGROUPS_PER_CU = 5
 PFSM_OPT_RESIDENT_TABLE = 6
+PFSM_OPT_MERGED_WALKS = 7
 
 # Exported symbols of libpfsm.so, as declared in include/pfsm.h.
 EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pattern", "pfsm_scan",
@@ -78,7 +79,8 @@ class _TuneReport(ctypes.Structure):
     _fields_ = [("segment", ctypes.c_int64), ("workgroups_per_cu", ctypes.c_int64),
                 ("table_budget", ctypes.c_int64), ("pair_cache", ctypes.c_int64),
                 ("ms_before", ctypes.c_double), ("ms_after", ctypes.c_double),
-                ("configs", ctypes.c_int32), ("pad", ctypes.c_int32), ("matches", ctypes.c_int64)]
+                ("configs", ctypes.c_int32), ("pad", ctypes.c_int32), ("matches", ctypes.c_int64),
+                ("merged_walks", ctypes.c_int64)]
 
 
 class _ServerStats(ctypes.Structure):

@@ -224,6 +224,7 @@ struct Knobs {
     int32_t wpc = 0;           // workgroups per compute unit
     int64_t table_budget = -1; // DFA: largest LDS-resident table
     int32_t pair_cache = 1;    // NFA: two-symbol cache allowed
+    int32_t merged = 0;        // DFA: tag-merged stepping
 };
 
 // Resident workgroups of a launch: `wpc` per compute unit (at most the

@@ -147,8 +147,33 @@ struct DfaArgs {
 // target by byte as 16-bit words (bit 15: live, bits 0-14: the state).
 constexpr int kDfaLdsFixed = kDfaWaves * kDfaRing + 256 * 2 + 256 * 2 + 256 * 2;
 
+// Tag-merged DFA scan: one wave per segment of kMergedSeg starts, for
+// automata with at most kMergedStates states (one entry per lane).
+constexpr int kMergedThreads = 256;
+constexpr int kMergedSeg = 1024;
+constexpr int kMergedStates = 63;
+
+struct MergedArgs {
+    const uint8_t *x;           // any alignment
+    int64_t n;
+    const uint8_t *tab;         // [n_states * 256] target by byte, 255 = none
+    const uint8_t *flags;       // [n_states] kLive | kFinal
+    const int32_t *lab_off;     // [n_states + 1]
+    const int32_t *lab;
+    int32_t n_states, q0;
+    MatchOut *out;
+    int64_t cap;
+    int64_t *total;
+    ScanCtl *ctl;
+    unsigned long long *lb;     // [lb_cap] look-back words, one per segment
+    int32_t lb_cap, n_segs;
+    long long *bstats;          // [gridDim.x * 4]
+};
+
 // Host-side kernel handles (defined in the .hip translation units).
 const void *dfa_kernel_fn(int enc, bool identity_map);
+hipError_t launch_dfa_merged(const MergedArgs &a, int grid, hipStream_t s);
+const void *dfa_merged_fn();
 hipError_t launch_write_zero(int64_t *p, hipStream_t stream);
 
 }  // namespace pfsmk

@@ -59,6 +59,10 @@ struct pfsm {
     int n_blocks = 0;
     int occ = 0, cus = 0;  // workgroups per compute unit that fit; compute units
     Knobs knobs;
+    // tag-merged scan (at most kMergedStates states): byte-indexed table
+    DevBuf d_mtab;
+    bool merged_ok = false;
+    int m_occ = 0;
     const void *kernel = nullptr;
     // ---- NFA
     NfaPtr nfa;
@@ -274,6 +278,24 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     h->occ = occ;
     h->cus = cus;
     h->n_blocks = grid_blocks(occ, cus, h->knobs.wpc);
+
+    // The tag-merged scan's table: target by byte, 255 = none.
+    h->merged_ok = false;
+    if (N <= kMergedStates) {
+        std::vector<uint8_t> mt((size_t)N * 256);
+        for (int32_t q = 0; q < N; ++q)
+            for (int b = 0; b < 256; ++b) {
+                const int sy = h->b2s[b];
+                const int32_t v = sy < 0 ? -1 : h->delta[(int64_t)q * S + sy];
+                mt[(size_t)q * 256 + b] = v < 0 ? 255 : (uint8_t)v;
+            }
+        if ((rc = h->d_mtab.upload(mt.data(), mt.size(), s))) return rc;
+        HIP_TRY(hipStreamSynchronize(s));
+        int mocc = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&mocc, dfa_merged_fn(), kMergedThreads, 0));
+        h->m_occ = mocc;
+        h->merged_ok = mocc > 0;
+    }
     return PFSM_OK;
 }
 
@@ -453,6 +475,41 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
     return PFSM_OK;
 }
 
+// One launch of the tag-merged scan (a single stream).
+static int merged_launch(pfsm_t *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap, int64_t *d_total,
+                         hipStream_t s) {
+    const int blocks = grid_blocks(h->m_occ, h->cus, h->knobs.wpc);
+    Workspace *w;
+    int rc = h->pool.get(s, blocks, &w);
+    if (rc) return rc;
+    const int64_t n_segs = (n + kMergedSeg - 1) / kMergedSeg;
+    if ((rc = grow_lb(w, (int)n_segs))) return rc;
+    MergedArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.x = x;
+    a.n = n;
+    a.tab = h->d_mtab.as<uint8_t>();
+    a.flags = h->d_flags.as<uint8_t>();
+    a.lab_off = h->d_lab_off.as<int32_t>();
+    a.lab = h->d_lab.as<int32_t>();
+    a.n_states = h->n_states;
+    a.q0 = h->q0;
+    a.out = out;
+    a.cap = cap;
+    a.total = d_total;
+    a.ctl = w->ctl;
+    a.lb = w->lb;
+    a.lb_cap = w->lb_cap;
+    a.n_segs = (int32_t)n_segs;
+    a.bstats = w->bstats;
+    const int waves = kMergedThreads / 64;
+    const int grid = (int)std::min<int64_t>((n_segs + waves - 1) / waves, blocks);
+    HIP_TRY(launch_dfa_merged(a, grid, s));
+    w->last_grid = grid;
+    h->pool.mark(w);
+    return PFSM_OK;
+}
+
 int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
                     int64_t *d_n_matches, void *hip_stream) {
     if (!h) return fail(PFSM_EINVAL, "NULL handle");
@@ -468,6 +525,8 @@ int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *
     }
     if (h->kind == 1)
         return nfa_scan_async(h->nfa.get(), d_input, n, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, s);
+    if (h->knobs.merged && h->merged_ok)
+        return merged_launch(h, d_input, n, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, s);
     return dfa_launch(h, d_input, n, nullptr, 0, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, s);
 }
 
@@ -512,6 +571,12 @@ int pfsm_set_option(pfsm_t *h, int32_t option, int64_t value, void *hip_stream) 
         k->table_budget = value;
         HIP_TRY(hipDeviceSynchronize());  // scans in flight read the current caches
         return dfa_upload_caches(h, s);
+    case PFSM_OPT_MERGED_WALKS:
+        if (value != 0 && value != 1) return fail(PFSM_EINVAL, "merged walks must be 0 or 1");
+        if (value == 1 && (h->kind == 1 || !h->merged_ok))
+            return fail(PFSM_ENOSYS, "tag-merged stepping needs a DFA with at most %d states", kMergedStates);
+        k->merged = (int32_t)value;
+        return PFSM_OK;
     case PFSM_OPT_PAIR_CACHE:
         if (h->kind == 0) return fail(PFSM_ENOSYS, "the pair cache applies to NFA handles");
         if (value != 0 && value != 1) return fail(PFSM_EINVAL, "pair cache must be 0 or 1");
@@ -538,8 +603,9 @@ int pfsm_get_option(const pfsm_t *h, int32_t option, int64_t *value) {
         *value = k->pair_cache;
         return PFSM_OK;
     case PFSM_OPT_MAX_WORKGROUPS_PER_CU:
-        *value = h->kind == 1 ? nfa_occupancy(h->nfa.get()) : h->occ;
+        *value = h->kind == 1 ? nfa_occupancy(h->nfa.get()) : (k->merged && h->merged_ok ? h->m_occ : h->occ);
         return PFSM_OK;
+    case PFSM_OPT_MERGED_WALKS: *value = k->merged; return PFSM_OK;
     case PFSM_OPT_RESIDENT_TABLE:
         if (h->kind == 1) return fail(PFSM_ENOSYS, "the table encoding applies to DFA handles");
         *value = (h->enc == kEnc8 || h->enc == kEnc8D || h->enc == kEnc16) ? 1 : 0;

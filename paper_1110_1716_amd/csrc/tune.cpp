@@ -1,9 +1,10 @@
-// Autotuner over a handle's launch settings: the bytes per segment (the
-// window a workgroup takes per ticket), resident workgroups per compute
-// unit, and the LDS budget of the read-only caches (a DFA's transition table
-// resident in LDS or read through L2 with hot rows cached; an NFA's
-// two-symbol cache on or off).  The number of starts per lane and of states
-// a lane keeps per walk are fixed when the kernels are compiled.
+// Autotuner over a handle's launch settings: tag-merged stepping (small
+// DFAs), the bytes per segment (the window a workgroup takes per ticket),
+// resident workgroups per compute unit, and the LDS budget of the read-only
+// caches (a DFA's transition table resident in LDS or read through L2 with
+// hot rows cached; an NFA's two-symbol cache on or off).  The number of
+// starts per lane and of states a lane keeps per walk are fixed when the
+// kernels are compiled.
 //
 // Settings are tried one knob at a time, each on a scan of a caller's
 // sample timed with HIP events, and a change is kept when it saves at least
@@ -97,12 +98,22 @@ int pfsm_tune(pfsm_t *h, const uint8_t *d_sample, int64_t n, int32_t reps, pfsm_
 
     if (!(rc = tm.time(&before))) {
         best = before;
-        // 1. LDS budget of the caches
+        // 0. tag-merged stepping, where the automaton allows it
         if (dfa) {
+            int64_t cur = 0;
+            pfsm_get_option(h, PFSM_OPT_MERGED_WALKS, &cur);
+            if (pfsm_set_option(h, PFSM_OPT_MERGED_WALKS, 1, hip_stream) == PFSM_OK &&
+                !(rc = pfsm_set_option(h, PFSM_OPT_MERGED_WALKS, cur, hip_stream)))
+                rc = tune_knob(PFSM_OPT_MERGED_WALKS, {0, 1});
+        }
+        int64_t merged = 0;
+        if (dfa) pfsm_get_option(h, PFSM_OPT_MERGED_WALKS, &merged);
+        // 1. LDS budget of the caches (the merged scan has its own table)
+        if (!rc && dfa) {
             int64_t resident = 0;
             pfsm_get_option(h, PFSM_OPT_RESIDENT_TABLE, &resident);
-            if (resident) rc = tune_knob(PFSM_OPT_TABLE_BUDGET, {-1, 0});
-        } else {
+            if (resident && !merged) rc = tune_knob(PFSM_OPT_TABLE_BUDGET, {-1, 0});
+        } else if (!rc) {
             rc = tune_knob(PFSM_OPT_PAIR_CACHE, {1, 0});
         }
         // 2. resident workgroups per compute unit
@@ -113,8 +124,8 @@ int pfsm_tune(pfsm_t *h, const uint8_t *d_sample, int64_t n, int32_t reps, pfsm_
             for (int64_t k = 1; k < occ; ++k) c.push_back(k);
             rc = tune_knob(PFSM_OPT_WORKGROUPS_PER_CU, c);
         }
-        // 3. bytes per segment
-        if (!rc) rc = tune_knob(PFSM_OPT_SEGMENT, {0, 4096, 8192, 16384, 32768, 65536});
+        // 3. bytes per segment (fixed in the merged scan)
+        if (!rc && !merged) rc = tune_knob(PFSM_OPT_SEGMENT, {0, 4096, 8192, 16384, 32768, 65536});
     }
     (void)hipEventDestroy(tm.e0);
     (void)hipEventDestroy(tm.e1);
@@ -130,6 +141,8 @@ int pfsm_tune(pfsm_t *h, const uint8_t *d_sample, int64_t n, int32_t reps, pfsm_
     report->ms_after = best;
     report->configs = tm.tried;
     report->matches = tm.count;
+    report->merged_walks = 0;
+    if (dfa) pfsm_get_option(h, PFSM_OPT_MERGED_WALKS, &report->merged_walks);
     return PFSM_OK;
 }
 
