@@ -9,18 +9,22 @@
 //     list of its tags, their number); a DFA with at most kMergedStates
 //     states never needs more than one entry per lane;
 //   * each step looks up one transition per entry, however many instances
-//     the entry holds, and adds the instance started at the current byte
-//     (while inside the segment) as a new entry in a free lane;
+//     the entry holds;
 //   * entries whose targets coincide merge: one lane wins the target in an
 //     LDS table, the others append their tag lists to its list through an
 //     atomic exchange of the list tail (tag lists are linked through an LDS
 //     array indexed by tag);
+//   * the instance started at the current byte (while inside the segment)
+//     joins the entry already in its state, else takes a free lane;
 //   * an entry in a final state reports every label for every tag it holds.
-// The wave walks its segment twice: a count pass records each tag's number
-// of matches, an exclusive scan over the tags and a decoupled look-back over
-// segments (in ticket order, as in the per-start scan) place them, and a
-// write pass stores them, so each start's matches come out in (end, label)
-// order and starts in increasing order.
+// A scan is three launches: a count launch walks every segment once and
+// stores each start's number of matches and the segment's total; one
+// workgroup scans the segment totals; a write launch walks every segment
+// again, turns its starts' counts into output offsets and stores the
+// matches, so each start's matches come out in (end, label) order and starts
+// in increasing order.  (A look-back between the two walks would make a
+// wave wait for every earlier segment's count walk, whose lengths vary with
+// the input.)
 //
 // A step costs a handful of LDS round trips whatever the number of live
 // instances, which pays when walks are long (an instance lives for many
@@ -38,15 +42,15 @@ constexpr int SEG = kMergedSeg;
 constexpr int WIN = 1024;  // staged bytes per wave window (16 per lane)
 
 __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
-    __shared__ uint8_t tab_s[kMergedStates * 256];
-    __shared__ uint8_t flags_s[64];
-    __shared__ int32_t laboff_s[65];
+    // tab_s: the table by byte in dynamic LDS (n_states * 256 bytes): the
+    // live target (bits 0-5) with bit 7 set when it is final, 255 = none
+    extern __shared__ __align__(16) uint8_t tab_s[];
+    __shared__ int32_t laboff_s[kMergedStates + 1];
     __shared__ int16_t next_s[MW][SEG];   // tag list links (-1: end)
     __shared__ long long kc_s[MW][SEG];   // matches per tag, then output offsets
     __shared__ uint8_t stage_s[MW][WIN];
     __shared__ int32_t own_s[MW][64], tail_s[MW][64], size_s[MW][64];
     __shared__ long long red4[4 * MW];
-    __shared__ unsigned epoch_s;
     __shared__ int last_s;
 
     const int tid = threadIdx.x;
@@ -54,11 +58,8 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
     const int lane = lane_id();
     const int N = a.n_states;
     for (int i = tid; i < N * 256; i += MT) tab_s[i] = a.tab[i];
-    for (int i = tid; i < N; i += MT) flags_s[i] = a.flags[i];
     for (int i = tid; i <= N; i += MT) laboff_s[i] = a.lab_off[i];
-    if (tid == 0) epoch_s = lb_epoch(a.ctl);
     __syncthreads();
-    const unsigned epoch = epoch_s;
     const int q0 = a.q0;
     const int dsh = (int)(reinterpret_cast<uintptr_t>(a.x) & 15);
     const uint8_t *xa = a.x - dsh;
@@ -70,6 +71,11 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
     int32_t *tailw = tail_s[wv];
     int32_t *sizew = size_s[wv];
     long long T = 0, X = 0, M = 0;
+    // the lane's 16 bytes of the staged window at wb (shifted positions)
+    auto fetch = [&](int64_t wb) __attribute__((always_inline)) {
+        const int64_t g0 = wb + 16 * lane;
+        return g0 >= 0 && g0 < nP ? load_granule(xa, g0) : make_uint4(0, 0, 0, 0);
+    };
 
     for (;;) {
         int sg = 0;
@@ -78,77 +84,129 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
         if (sg >= a.n_segs) break;
         const int64_t lo = (int64_t)sg * SEG;
         const int64_t hi = lo + SEG < a.n ? lo + SEG : a.n;
+        const int pass = a.pass;
         long long base = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-            if (pass == 0)
-                for (int g = lane; g < SEG; g += 64) kc[g] = 0;
-            // the lane's entry: state (-1: none), tag list, instance count
+        if (pass == 0) {
+            for (int g = lane; g < SEG; g += 64) kc[g] = 0;
+        } else {
+            // this segment's starts: output offsets from their counts
+            base = a.seg_base[sg];
+            if (a.seg_base[sg + 1] == base) continue;  // no matches
+            constexpr int PER = SEG / 64;
+            long long own_sum = 0;
+            for (int j = 0; j < PER; ++j) {
+                const int64_t i = lo + lane * PER + j;
+                const long long c = i < hi ? a.tag_cnt[i] : 0;
+                kc[lane * PER + j] = c;
+                own_sum += c;
+            }
+            const long long inc = wave_incl_scan(own_sum);
+            long long run = inc - own_sum;
+            for (int j = 0; j < PER; ++j) {
+                const long long c = kc[lane * PER + j];
+                kc[lane * PER + j] = run;
+                run += c;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        {
+            // the lane's entry: state (-1: none) and whether it is final, its
+            // tag list and instance count
             int st = -1, head = -1, tail = -1, sz = 0;
-            bool any = false;
-            int64_t wb = -1;  // staged window (shifted positions)
+            bool stf = false, any = false;
+            // stage the first window, request the next; bn: the next byte
+            int64_t wb = (lo + dsh) & ~(int64_t)(WIN - 1);
+            const uint4 first = fetch(wb);
+            uint4 pre = fetch(wb + WIN);
+            __builtin_amdgcn_wave_barrier();
+            *reinterpret_cast<uint4 *>(stage + 16 * lane) = first;
+            __builtin_amdgcn_wave_barrier();
+            int bn = stage[lo + dsh - wb];
             for (int64_t p = lo; p < a.n && (p < hi || any); ++p) {
-                const int64_t ps = p + dsh;
-                if (ps >= wb + WIN || wb < 0) {
-                    wb = ps & ~(int64_t)(WIN - 1);
-                    const int64_t g0 = wb + 16 * lane;
-                    const uint4 v = g0 < nP ? load_granule(xa, g0) : make_uint4(0, 0, 0, 0);
+                const int b = bn;
+                const int64_t ps1 = p + 1 + dsh;
+                if (ps1 >= wb + WIN) {
+                    wb += WIN;
                     __builtin_amdgcn_wave_barrier();
-                    *reinterpret_cast<uint4 *>(stage + 16 * lane) = v;
+                    *reinterpret_cast<uint4 *>(stage + 16 * lane) = pre;
                     __builtin_amdgcn_wave_barrier();
+                    pre = fetch(wb + WIN);
                 }
-                const int b = stage[ps - wb];
+                bn = stage[ps1 - wb];
                 // step every entry (one lookup per entry, whatever it holds)
-                int t = -1;
+                // and find the state of the instance started here
+                int t = -1, t0 = -1;
+                bool tf = false, t0f = false;
                 if (st >= 0) {
                     const int v = tab_s[st * 256 + b];
-                    t = v != 255 && (flags_s[v] & kLive) ? v : -1;
-                    if (pass == 0) {
-                        T += sz;
-                        X += t >= 0 ? sz : 0;
+                    t = v == 255 ? -1 : (v & 63);
+                    tf = v != 255 && (v & 128);
+                }
+                if (p < hi) {
+                    const int v = tab_s[q0 * 256 + b];
+                    t0 = v == 255 ? -1 : (v & 63);
+                    t0f = v != 255 && (v & 128);
+                }
+                if (pass == 0) {
+                    T += sz;
+                    X += t >= 0 ? sz : 0;
+                    if (p < hi && lane == 0) {
+                        ++T;
+                        X += t0 >= 0 ? 1 : 0;
                     }
                 }
-                // the instance started here, in the first free lane
-                const unsigned long long used = __ballot(st >= 0);
-                if (p < hi) {
-                    const int f = __ffsll((long long)~used) - 1;
-                    if (lane == f) {
-                        const int g = (int)(p - lo);
-                        const int v = tab_s[q0 * 256 + b];
-                        t = v != 255 && (flags_s[v] & kLive) ? v : -1;
-                        head = tail = g;
-                        sz = 1;
-                        nxt[g] = -1;
-                        if (pass == 0) {
-                            ++T;
-                            X += t >= 0 ? 1 : 0;
+                // entries whose targets coincide merge into one lane (only
+                // possible with two or more survivors)
+                const unsigned long long alive = __ballot(t >= 0);
+                bool win = t >= 0;
+                if (__popcll(alive) >= 2) {
+                    if (t >= 0) own[t] = lane;
+                    __builtin_amdgcn_wave_barrier();
+                    win = t >= 0 && own[t] == lane;
+                    const bool lose = t >= 0 && !win;
+                    if (__any(lose)) {
+                        if (win) {
+                            tailw[t] = tail;
+                            sizew[t] = sz;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        if (lose) {
+                            const int old = atomicExch(&tailw[t], tail);
+                            nxt[old] = (int16_t)head;
+                            atomicAdd(&sizew[t], sz);
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        if (win) {
+                            tail = tailw[t];
+                            sz = sizew[t];
                         }
                     }
                 }
-                // entries whose targets coincide merge into one lane
-                if (t >= 0) own[t] = lane;
-                __builtin_amdgcn_wave_barrier();
-                const bool win = t >= 0 && own[t] == lane;
-                const bool lose = t >= 0 && !win;
-                if (__any(lose)) {
-                    if (win) {
-                        tailw[t] = tail;
-                        sizew[t] = sz;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    if (lose) {
-                        const int old = atomicExch(&tailw[t], tail);
-                        nxt[old] = (int16_t)head;
-                        atomicAdd(&sizew[t], sz);
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    if (win) {
-                        tail = tailw[t];
-                        sz = sizew[t];
+                st = win ? t : -1;
+                stf = win && tf;
+                if (!win) sz = 0;
+                // the new instance joins the entry in its state, or takes a
+                // free lane (entries hold distinct states, at most 63)
+                if (t0 >= 0) {
+                    const int g = (int)(p - lo);
+                    const unsigned long long hit = __ballot(st == t0);
+                    const int w = hit ? __ffsll((long long)hit) - 1 : __ffsll((long long)~__ballot(st >= 0)) - 1;
+                    if (lane == w) {
+                        nxt[g] = -1;
+                        if (hit) {
+                            nxt[tail] = (int16_t)g;
+                            tail = g;
+                            ++sz;
+                        } else {
+                            st = t0;
+                            stf = t0f;
+                            head = tail = g;
+                            sz = 1;
+                        }
                     }
                 }
-                st = win ? t : -1;
                 // report: every tag of an entry in a final state
-                const bool fin = st >= 0 && (flags_s[st] & kFinal);
+                const bool fin = st >= 0 && stf;
                 if (__any(fin)) {
                     if (fin) {
                         const int l0 = laboff_s[st], l1 = laboff_s[st + 1];
@@ -177,40 +235,63 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
                 any = __any(st >= 0);
             }
             if (pass == 0) {
-                // per-tag offsets within the segment, then the segment's base
+                // each start's count, and the segment's total
                 __builtin_amdgcn_wave_barrier();
-                constexpr int PER = SEG / 64;
-                long long own_sum = 0;
-                for (int j = 0; j < PER; ++j) own_sum += kc[lane * PER + j];
-                const long long inc = wave_incl_scan(own_sum);
-                const long long seg_total = __shfl(inc, 63);
-                long long run = inc - own_sum;
-                for (int j = 0; j < PER; ++j) {
-                    const long long c = kc[lane * PER + j];
-                    kc[lane * PER + j] = run;
-                    run += c;
+                long long sum = 0;
+                for (int g = lane; g < SEG; g += 64) {
+                    const int64_t i = lo + g;
+                    if (i < hi) {
+                        a.tag_cnt[i] = kc[g];
+                        sum += kc[g];
+                    }
                 }
-                __builtin_amdgcn_wave_barrier();
-                const long long ex = lookback(a.lb, sg, epoch, seg_total);
-                base = ex;
-                if (sg == a.n_segs - 1 && lane == 0) *a.total = ex + seg_total;
-                if (seg_total == 0) break;
+                sum = wave_sum(sum);
+                if (lane == 0) a.seg_cnt[sg] = sum;
             }
         }
     }
-    long long st4[4] = {T, X, 0, M};
-    block_sum4<MT>(st4, red4);
-    if (tid == 0) {
+    if (a.pass == 0) {
+        long long st4[4] = {T, X, 0, M};
+        block_sum4<MT>(st4, red4);
+        if (tid == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a.bstats[4 * blockIdx.x + k] = st4[k];
+            for (int k = 0; k < 4; ++k) a.bstats[4 * blockIdx.x + k] = st4[k];
+        }
     }
     finish_launch<MT>(a.ctl, a.lb, a.lb_cap, &last_s);
 }
 
+// Exclusive scan of the segment totals (one workgroup): seg_base[s] for
+// s <= n_segs, and the grand total.
+__global__ __launch_bounds__(1024) void merged_seg_scan_kernel(const long long *seg_cnt, int n_segs,
+                                                               long long *seg_base, int64_t *total) {
+    __shared__ long long red[16];
+    long long run = 0;
+    for (int c0 = 0; c0 < n_segs; c0 += 1024) {
+        const int s = c0 + threadIdx.x;
+        long long tot;
+        const long long ex = block_excl_scan<1024>(s < n_segs ? seg_cnt[s] : 0, red, &tot);
+        if (s < n_segs) seg_base[s] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        seg_base[n_segs] = run;
+        *total = run;
+    }
+}
+
 }  // namespace
 
-hipError_t launch_dfa_merged(const MergedArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(dfa_merged_kernel, dim3(grid), dim3(MT), 0, s, a);
+hipError_t launch_dfa_merged(const MergedArgs &a0, int grid, hipStream_t s) {
+    MergedArgs a = a0;
+    a.pass = 0;
+    hipLaunchKernelGGL(dfa_merged_kernel, dim3(grid), dim3(MT), merged_lds(a.n_states), s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(merged_seg_scan_kernel, dim3(1), dim3(1024), 0, s, a.seg_cnt, a.n_segs, a.seg_base, a.total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    a.pass = 1;
+    hipLaunchKernelGGL(dfa_merged_kernel, dim3(grid), dim3(MT), merged_lds(a.n_states), s, a);
     return hipGetLastError();
 }
 

@@ -100,6 +100,9 @@ struct Workspace {
     uint64_t used = 0;                    // launch sequence number of the last scan
     uint8_t *stage = nullptr;             // aligned copy of a misaligned input
     int64_t stage_cap = 0;
+    long long *m_tag = nullptr;           // tag-merged scan: matches per start
+    long long *m_seg = nullptr;           //   per segment, then their scan
+    int64_t c_m_tag = 0, c_m_seg = 0;
     uint32_t *big_front = nullptr;        // NFA replay frontiers
     uint32_t *big_bits = nullptr;         // NFA replay visited bits (kept clear)
     int64_t big_states = 0;
@@ -114,6 +117,8 @@ struct Workspace {
         if (h_total) (void)hipHostFree(h_total);
         if (h_stats) (void)hipHostFree(h_stats);
         if (stage) (void)hipFree(stage);
+        if (m_tag) (void)hipFree(m_tag);
+        if (m_seg) (void)hipFree(m_seg);
         if (big_front) (void)hipFree(big_front);
         if (big_bits) (void)hipFree(big_bits);
     }

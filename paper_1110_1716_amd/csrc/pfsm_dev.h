@@ -153,21 +153,27 @@ constexpr int kMergedThreads = 256;
 constexpr int kMergedSeg = 1024;
 constexpr int kMergedStates = 63;
 
+// Dynamic LDS of the tag-merged scan: its byte-indexed table.
+inline size_t merged_lds(int n_states) { return ((size_t)n_states * 256 + 15) / 16 * 16; }
+
 struct MergedArgs {
     const uint8_t *x;           // any alignment
     int64_t n;
-    const uint8_t *tab;         // [n_states * 256] target by byte, 255 = none
-    const uint8_t *flags;       // [n_states] kLive | kFinal
+    const uint8_t *tab;         // [n_states * 256] by byte: live target | 128 when final, 255 = none
     const int32_t *lab_off;     // [n_states + 1]
     const int32_t *lab;
     int32_t n_states, q0;
     MatchOut *out;
     int64_t cap;
     int64_t *total;
-    ScanCtl *ctl;
-    unsigned long long *lb;     // [lb_cap] look-back words, one per segment
+    ScanCtl *ctl;               // segment tickets
+    unsigned long long *lb;     // look-back words (reset by the last workgroup; unused otherwise)
     int32_t lb_cap, n_segs;
-    long long *bstats;          // [gridDim.x * 4]
+    long long *bstats;          // [gridDim.x * 4] (count launch)
+    long long *tag_cnt;         // [n] matches of each start (count launch writes, write launch reads)
+    long long *seg_cnt;         // [n_segs] matches of each segment
+    long long *seg_base;        // [n_segs + 1] their exclusive scan
+    int32_t pass;               // 0: count launch, 1: write launch
 };
 
 // Host-side kernel handles (defined in the .hip translation units).

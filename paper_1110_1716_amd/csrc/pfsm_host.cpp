@@ -279,7 +279,8 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     h->cus = cus;
     h->n_blocks = grid_blocks(occ, cus, h->knobs.wpc);
 
-    // The tag-merged scan's table: target by byte, 255 = none.
+    // The tag-merged scan's table by byte: the live target, with bit 7 set
+    // when it is final; 255 = no live target.
     h->merged_ok = false;
     if (N <= kMergedStates) {
         std::vector<uint8_t> mt((size_t)N * 256);
@@ -287,12 +288,15 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
             for (int b = 0; b < 256; ++b) {
                 const int sy = h->b2s[b];
                 const int32_t v = sy < 0 ? -1 : h->delta[(int64_t)q * S + sy];
-                mt[(size_t)q * 256 + b] = v < 0 ? 255 : (uint8_t)v;
+                const bool ok = v >= 0 && (flags[v] & kLive);
+                mt[(size_t)q * 256 + b] = ok ? (uint8_t)(v | ((flags[v] & kFinal) ? 128 : 0)) : 255;
             }
         if ((rc = h->d_mtab.upload(mt.data(), mt.size(), s))) return rc;
         HIP_TRY(hipStreamSynchronize(s));
+        const void *mk = dfa_merged_fn();
+        HIP_TRY(hipFuncSetAttribute(mk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)merged_lds(N)));
         int mocc = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&mocc, dfa_merged_fn(), kMergedThreads, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&mocc, mk, kMergedThreads, merged_lds(N)));
         h->m_occ = mocc;
         h->merged_ok = mocc > 0;
     }
@@ -483,13 +487,23 @@ static int merged_launch(pfsm_t *h, const uint8_t *x, int64_t n, MatchOut *out, 
     int rc = h->pool.get(s, blocks, &w);
     if (rc) return rc;
     const int64_t n_segs = (n + kMergedSeg - 1) / kMergedSeg;
-    if ((rc = grow_lb(w, (int)n_segs))) return rc;
+    auto grow_ll = [&](long long **p, int64_t *c, int64_t need) -> int {
+        if (need <= *c) return PFSM_OK;
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*p) HIP_TRY(hipFree(*p));
+        *p = nullptr;
+        *c = 0;
+        HIP_TRY(hipMalloc(p, sizeof(long long) * (size_t)need));
+        *c = need;
+        return PFSM_OK;
+    };
+    if ((rc = grow_ll(&w->m_tag, &w->c_m_tag, n)) || (rc = grow_ll(&w->m_seg, &w->c_m_seg, 2 * n_segs + 1)))
+        return rc;
     MergedArgs a;
     std::memset(&a, 0, sizeof a);
     a.x = x;
     a.n = n;
     a.tab = h->d_mtab.as<uint8_t>();
-    a.flags = h->d_flags.as<uint8_t>();
     a.lab_off = h->d_lab_off.as<int32_t>();
     a.lab = h->d_lab.as<int32_t>();
     a.n_states = h->n_states;
@@ -502,6 +516,9 @@ static int merged_launch(pfsm_t *h, const uint8_t *x, int64_t n, MatchOut *out, 
     a.lb_cap = w->lb_cap;
     a.n_segs = (int32_t)n_segs;
     a.bstats = w->bstats;
+    a.tag_cnt = w->m_tag;
+    a.seg_cnt = w->m_seg;
+    a.seg_base = w->m_seg + n_segs;
     const int waves = kMergedThreads / 64;
     const int grid = (int)std::min<int64_t>((n_segs + waves - 1) / waves, blocks);
     HIP_TRY(launch_dfa_merged(a, grid, s));
