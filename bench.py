@@ -8,7 +8,10 @@ resident in HBM before timing starts and rotate through 64 distinct copies
 
 Prints one JSON line with GB/s (value), transitions/s, the single-scan
 latency distribution of the synchronous call, the roofline position of the
-scan kernel and the CPU oracle's throughput on the host cores.
+scan kernel and the CPU oracle's throughput on the host cores, followed by
+the batched, served, long-walk, streamed and autotuned measurements (each
+can be skipped).  --workload cfg3 or log measures the NFA union or the
+tag-merged log search the same way instead (for profiling runs).
 """
 from __future__ import annotations
 
@@ -33,6 +36,9 @@ ROTATE_BYTES = 1 << 30
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("cfg2", "cfg3", "log"), default="cfg2",
+                    help="cfg2: the 256-state DFA (reported line); cfg3: the 2,000-signature NFA union; "
+                         "log: line-bounded log search with tag-merged stepping (profiling runs)")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--latency-iters", type=int, default=2000)
@@ -44,24 +50,35 @@ def parse():
     ap.add_argument("--batch-replays", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) measurement")
     ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--no-long", action="store_true", help="skip the long-walk (tag-merged vs per-start) measurement")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming (pieces vs whole) measurement")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner report")
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ["paper_1110_1716_amd/csrc/dfa_scan.hip", "paper_1110_1716_amd/csrc/scan_common.h",
-                  "paper_1110_1716_amd/csrc/pfsm_dev.h"]
-TRAFFIC_PROFILE = "profiles/dfa_scan_cfg2_hbm_traffic.txt"
+KERNEL_SOURCES = {
+    "cfg2": ["paper_1110_1716_amd/csrc/dfa_scan.hip", "paper_1110_1716_amd/csrc/scan_common.h",
+             "paper_1110_1716_amd/csrc/pfsm_dev.h"],
+    "cfg3": ["paper_1110_1716_amd/csrc/nfa_scan.hip", "paper_1110_1716_amd/csrc/scan_common.h",
+             "paper_1110_1716_amd/csrc/pfsm_dev.h"],
+    "log": ["paper_1110_1716_amd/csrc/dfa_merged.hip", "paper_1110_1716_amd/csrc/scan_common.h",
+            "paper_1110_1716_amd/csrc/pfsm_dev.h"],
+}
+TRAFFIC_PROFILE = {"cfg2": "profiles/dfa_scan_cfg2_hbm_traffic.txt",
+                   "cfg3": "profiles/nfa_scan_cfg3_hbm_traffic.txt",
+                   "log": "profiles/dfa_merged_log_hbm_traffic.txt"}
 
 
-def measured_traffic():
+def measured_traffic(workload: str = "cfg2"):
     """HBM bytes per launch of the scan kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by what it reads
     for a plain copy of known size), or None when the kernel sources have
     changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    path = os.path.join(ROOT, TRAFFIC_PROFILE[workload])
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[workload]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     fields = {}
@@ -214,6 +231,102 @@ def served(n_req: int):
     return res
 
 
+def _time_async(P, h, x, out, cnt, reps):
+    import torch
+    P.pfsm_scan_async(h, x, out, cnt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.pfsm_scan_async(h, x, out, cnt)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def long_walks(n: int = 16 << 20):
+    """Line-bounded log search (every start lives to the end of its line):
+    one walk per start against tag-merged stepping, same input and results."""
+    import torch
+    import workloads as W
+    import paper_1110_1716_amd as P
+    wl = W.log_search(n=n)
+    h = P.pfsm_load(wl.automaton)
+    x = torch.from_numpy(wl.data).cuda()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    res = {"workload": wl.name, "n_bytes": n, "seed": wl.seed}
+    counts = {}
+    try:
+        for merged, reps, key in ((0, 3, "per_start"), (1, 20, "merged")):
+            P.pfsm_set_option(h, P.PFSM_OPT_MERGED_WALKS, merged)
+            m, out = P.pfsm_scan(h, x)
+            st = P.pfsm_last_stats(h)
+            ms = _time_async(P, h, x, out, cnt, reps)
+            counts[key] = (m, int(cnt.item()))
+            res[key] = {"ms": round(ms, 3), "GB/s": round(n / ms / 1e6, 3),
+                        "transitions_per_s": round(st["transitions"] / ms * 1e3, 1)}
+            res["transitions_per_scan"] = int(st["transitions"])
+            res["matches"] = int(m)
+            del out
+    finally:
+        h.free()
+    if len({v for pair in counts.values() for v in pair}) != 1:
+        raise SystemExit(f"long-walk counts differ: {counts}")
+    res["speedup"] = round(res["per_start"]["ms"] / res["merged"]["ms"], 2)
+    return res
+
+
+def streamed(piece_sizes=(1 << 20, 4 << 20), passes: int = 3):
+    """The bench workload fed through pfsm_stream_feed in pieces (instances
+    live at a piece's end carried into the next) against one whole scan."""
+    import torch
+    import workloads as W
+    import paper_1110_1716_amd as P
+    wl = W.cfg2()
+    n = wl.data.size
+    h = P.pfsm_load(wl.automaton)
+    x = torch.from_numpy(wl.data).cuda()
+    out = torch.empty((n // 16 + 4096, 3), dtype=torch.int32, device="cuda")
+    res = {"workload": wl.name, "n_bytes": n, "passes": passes}
+    try:
+        whole, _ = P.pfsm_scan(h, x, out=out)
+        for k in piece_sizes:
+            with P.Stream(h) as st:
+                for lo in range(0, n, k):  # warm-up pass (buffers grown)
+                    st.feed(x[lo:lo + k], out=out)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tot = 0
+                for _ in range(passes):
+                    for lo in range(0, n, k):
+                        m, _ = st.feed(x[lo:lo + k], out=out)
+                        tot += m
+                dt = (time.perf_counter() - t0) / passes
+            if tot != passes * whole:
+                raise SystemExit(f"streamed matches {tot // passes} differ from one scan's {whole}")
+            res[f"pieces_{k >> 20}MiB"] = {"ms_per_pass": round(dt * 1e3, 3), "GB/s": round(n / dt / 1e9, 2),
+                                            "us_per_piece": round(dt * 1e6 / ((n + k - 1) // k), 1)}
+        res["matches_per_pass"] = int(whole)
+    finally:
+        h.free()
+    return res
+
+
+def autotune():
+    """What the autotuner keeps for the bench workload (a separate handle;
+    the timed handle above runs the default settings)."""
+    import torch
+    import workloads as W
+    import paper_1110_1716_amd as P
+    wl = W.cfg2()
+    h = P.pfsm_load(wl.automaton)
+    try:
+        rep = P.pfsm_tune(h, torch.from_numpy(wl.data).cuda(), reps=20)
+    finally:
+        h.free()
+    return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep.items()}
+
+
 def cpu_baseline(wl, seconds: float):
     """The oracle as it is, on the host cores, over repeated passes of the
     same 16 MiB input until `seconds` of wall time have been spent."""
@@ -246,14 +359,17 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wl = W.cfg2()
+    wl = {"cfg2": W.cfg2, "cfg3": W.cfg3, "log": W.log_search}[args.workload]()
     n = wl.data.size
     h = P.pfsm_load(wl.automaton)
+    kernel = {"cfg2": "dfa_scan_kernel", "cfg3": "nfa_scan_kernel", "log": "dfa_merged_kernel"}[args.workload]
+    if args.workload == "log":
+        P.pfsm_set_option(h, P.PFSM_OPT_MERGED_WALKS, 1)
 
     host = torch.from_numpy(wl.data.copy())
     n_copies = max(1, ROTATE_BYTES // n)
     xs = [host.to(dev) for _ in range(n_copies)]
-    cap = n // 8 + 4096
+    cap = n // 8 + 4096 if args.workload != "log" else n + 4096
     out = torch.empty((cap, 3), dtype=torch.int32, device=dev)
     counts = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
@@ -324,27 +440,33 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n_bytes": n, "seed": wl.seed, "n_states": 256,
-                   "n_symbols": 256, "finals": 16, "matches_per_scan": int(n_ref),
-                   "resident_input_copies": n_copies},
+        "config": {"workload": wl.name, "n_bytes": n, "seed": wl.seed,
+                   "n_states": int(wl.automaton.n_states), "kind": wl.automaton.kind,
+                   "matches_per_scan": int(n_ref), "resident_input_copies": n_copies},
         "transitions_per_s": round(tps, 1),
         "transitions_per_scan": int(transitions),
         "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                        "p99": round(float(np.percentile(lat_us, 99)), 2),
                        "iters": args.latency_iters, "call": "pfsm_scan (synchronous)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "dfa_scan_kernel", "kernel_avg_us": round(kern_avg_s * 1e6, 3),
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.workload),
+                     "kernel": kernel, "kernel_avg_us": round(kern_avg_s * 1e6, 3),
                      "alg_bytes_per_launch": int(alg_bytes)},
         "wall_s_timed": round(wall, 4),
     }
     h.free()
-    if not args.no_batch:
-        res["batched"] = batched_vs_plain(args.batch_replays)
-    if not args.no_serve:
-        res["served"] = served(args.serve_requests)
-    if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    sections = [("batched", args.no_batch, lambda: batched_vs_plain(args.batch_replays)),
+                ("served", args.no_serve, lambda: served(args.serve_requests)),
+                ("long_walks", args.no_long, long_walks),
+                ("streamed", args.no_stream, streamed),
+                ("autotune", args.no_tune, autotune),
+                ("cpu_baseline", args.no_cpu, lambda: cpu_baseline(wl, args.cpu_seconds))]
+    print(f"bench: {args.workload} scan timed", file=sys.stderr, flush=True)
+    for key, skip, fn in sections:
+        if not skip:
+            res[key] = fn()
+            print(f"bench: {key} done", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 
 
