@@ -275,3 +275,26 @@ def test_invalid_descriptor_rejected():
     d.delta[3] = 99
     with pytest.raises(ValueError):
         oracle.scan(d, b"ab")
+
+
+def test_log_search_equals_definition():
+    # the long-walk workload's search DFA against its plain definition:
+    # (s, e) matches when x[s..e] holds no newline and ends with the pattern
+    wl = W.log_search(n=1 << 16, line_mean=256)
+    x = bytes(wl.data)
+    ref, wk = oracle.scan(wl.automaton, x)
+    exp = []
+    for e in range(4, len(x)):
+        if x[e - 4:e + 1] == b"ERROR":
+            s = e - 4
+            while s >= 0 and x[s] != ord("\n"):
+                exp.append((s, e, 0))
+                s -= 1
+    exp = np.array(sorted(exp), np.int32).reshape(-1, 3)
+    assert len(exp) > 100
+    assert np.array_equal(ref, exp)
+    # every start lives to the end of its line (or of the input)
+    nl = [i for i, c in enumerate(x) if c == ord("\n")]
+    ends = np.searchsorted(np.array(nl), np.arange(len(x)))
+    steps = [(nl[k] if k < len(nl) else len(x) - 1) - s + 1 for s, k in enumerate(ends)]
+    assert wk["T"] == sum(steps)
