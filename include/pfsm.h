@@ -298,12 +298,14 @@ void pfsm_stream_close(pfsm_stream_t *st);
  * Serving loop: continuous batching of scan requests (the online use of
  * Section I) against resident handles.  A worker thread admits queued
  * requests, first come first served, into one of two batches while their
- * bytes plus an output estimate (n/16 + 256 matches each, charged twice for
- * the device and host copies) fit `mem_budget` bytes, and runs each batch
- * as pfsm_scan_batch does on a stream of its own; a request arriving while
- * batches run joins the next one as soon as a batch slot and memory free up.
- * A request larger than the budget runs alone.  Each request's matches are
- * exactly those of pfsm_scan on its bytes alone.
+ * bytes plus reserved output rows fit `mem_budget` bytes.  The reservation
+ * is 1.5 times the matches per byte seen so far on the request's automaton
+ * (n/16 before any), plus 256, charged twice for the device and host copies;
+ * a request whose matches outgrow it is run again with its exact count.
+ * Each batch runs as pfsm_scan_batch does, on a stream of its own; a request
+ * arriving while batches run joins the next one as soon as a batch slot and
+ * memory free up.  A request larger than the budget runs alone.  Each
+ * request's matches are exactly those of pfsm_scan on its bytes alone.
  * --------------------------------------------------------------------- */
 typedef struct pfsm_server pfsm_server_t;
 

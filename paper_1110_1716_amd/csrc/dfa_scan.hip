@@ -404,6 +404,29 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     uint32_t *lst = reinterpret_cast<uint32_t *>(lds + a.off_list) + wv * kDfaList;
     QEnt *spill = reinterpret_cast<QEnt *>(a.spill) + (int64_t)b * kDfaSpill;
 
+    // Every load of the start-up is issued before any is waited for: the LDS
+    // image (flags, label CSR, table) in one run of 16-byte loads, q0's row,
+    // and the first segment ticket.
+    const uint4 *isrc = reinterpret_cast<const uint4 *>(a.res);
+    uint4 *idst = reinterpret_cast<uint4 *>(lds + a.off_flags);
+    const int n16 = a.res_bytes >> 4;
+    int ib = 0;
+    for (; ib + 5 * NT < n16; ib += 6 * NT) {
+        const uint4 v0 = isrc[ib + tid], v1 = isrc[ib + NT + tid], v2 = isrc[ib + 2 * NT + tid],
+                    v3 = isrc[ib + 3 * NT + tid], v4 = isrc[ib + 4 * NT + tid], v5 = isrc[ib + 5 * NT + tid];
+        idst[ib + tid] = v0;
+        idst[ib + NT + tid] = v1;
+        idst[ib + 2 * NT + tid] = v2;
+        idst[ib + 3 * NT + tid] = v3;
+        idst[ib + 4 * NT + tid] = v4;
+        idst[ib + 5 * NT + tid] = v5;
+    }
+    int fq = -1, fslot = -1, fb = -1;
+    if (tid < 256) {
+        fq = a.first[tid];
+        fslot = a.first_slot[tid];
+        fb = a.b2s[tid];
+    }
     if (tid == 0) {
         seg_s = take_ticket(a.ctl);
         epoch_s = lb_epoch(a.ctl);
@@ -417,6 +440,12 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         ovf = 0;
         sp_n = 0;
     }
+    for (int i = ib + tid; i < n16; i += NT) idst[i] = isrc[i];
+    if (tid < 256) {
+        f16_s[tid] = fq >= 0 ? (uint16_t)(0x8000u | ((unsigned)fq & 0x7fffu)) : (uint16_t)0;
+        slot_s[tid] = (int16_t)fslot;
+        b2s_s[tid] = (int16_t)fb;
+    }
     __syncthreads();
     const int n_segs = nsegs_s;
     if (seg_s >= n_segs) {
@@ -429,34 +458,6 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     const int seg_base = segbase_s;
     const long long out_base = base_s;
     const int64_t seg_bytes = segsz_s;
-    // Tables into LDS: every load of a thread is issued before its stores.
-    if (tid < 256) {
-        const int f = a.first[tid];
-        f16_s[tid] = f >= 0 ? (uint16_t)(0x8000u | ((unsigned)f & 0x7fffu)) : (uint16_t)0;
-        slot_s[tid] = a.first_slot[tid];
-        b2s_s[tid] = a.b2s[tid];
-    }
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.res);
-        uint4 *dst = reinterpret_cast<uint4 *>(tab_s);
-        const int n16 = a.res_bytes >> 4;
-        int i = tid;
-        for (; i + 3 * NT < n16; i += 4 * NT) {
-            const uint4 v0 = src[i], v1 = src[i + NT], v2 = src[i + 2 * NT], v3 = src[i + 3 * NT];
-            dst[i] = v0;
-            dst[i + NT] = v1;
-            dst[i + 2 * NT] = v2;
-            dst[i + 3 * NT] = v3;
-        }
-        for (; i < n16; i += NT) dst[i] = src[i];
-    }
-    if (DfaCtx<ENC, kId>::kResident) {
-        for (int i = tid; i < a.n_states; i += NT) flags_s[i] = a.flags[i];
-        for (int i = tid; i <= a.n_states; i += NT) laboff_s[i] = a.lab_off[i];
-        const int nnz = a.lab_off[a.n_states];
-        for (int i = tid; i < nnz; i += NT) lab_s[i] = a.lab[i];
-    }
-    __syncthreads();
     const unsigned epoch = epoch_s;
 
     DfaCtx<ENC, kId> c{a, ring, f16_s, slot_s, b2s_s, flags_s, laboff_s, lab_s, tab_s, mkey, mend, mlab, &mn, &ovf};

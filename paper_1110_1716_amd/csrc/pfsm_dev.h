@@ -116,7 +116,7 @@ struct DfaArgs {
     const uint8_t *x;           // 16-byte aligned
     int64_t n;
     const void *tbl;            // table as stored in HBM (int16 or int32)
-    const void *res;            // resident encoding image (LDS copy source)
+    const void *res;            // LDS image from off_flags on: flags, label CSR, table (or cached rows)
     int32_t res_bytes;
     int32_t n_states, n_symbols;
     const int16_t *b2s;         // [256] byte -> symbol, -1 = not in the alphabet

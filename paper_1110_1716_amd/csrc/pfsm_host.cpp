@@ -254,17 +254,29 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     h->lds_bytes = h->off_list + kDfaWaves * kDfaList * 4;
     if (h->lds_bytes > kDfaLdsLimit) return fail(PFSM_EINVAL, "DFA scan LDS layout does not fit");
 
+    // The LDS image from off_flags to the end of the table: flags, label CSR
+    // (resident encodings) and the table or cached rows, in LDS layout, so
+    // that the kernel copies it with one run of loads.
+    std::vector<uint8_t> img((size_t)(h->off_tab - h->off_flags) + res.size(), 0);
+    if (resident) {
+        std::memcpy(img.data(), flags.data(), (size_t)N);
+        std::memcpy(img.data() + (h->off_laboff - h->off_flags), off.data(), sizeof(int32_t) * (size_t)(N + 1));
+        if (!lab.empty())
+            std::memcpy(img.data() + (h->off_lab - h->off_flags), lab.data(), sizeof(int32_t) * lab.size());
+    }
+    std::memcpy(img.data() + (h->off_tab - h->off_flags), res.data(), res.size());
+
     int rc;
     if ((rc = h->d_first.upload(first.data(), 256, s))) return rc;
     if ((rc = h->d_first_slot.upload(first_slot.data(), 256, s))) return rc;
-    if ((rc = h->d_res.upload(res.data(), res.size(), s))) return rc;
+    if ((rc = h->d_res.upload(img.data(), img.size(), s))) return rc;
     if ((rc = h->d_flags.upload(flags.data(), N, s))) return rc;
     if ((rc = h->d_lab_off.upload(off.data(), N + 1, s))) return rc;
     if ((rc = h->d_lab.upload(lab.data(), lab.size(), s))) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     h->enc = enc;
     h->n_hot = n_hot;
-    h->res_bytes = (int32_t)res.size();
+    h->res_bytes = (int32_t)img.size();
 
     h->dev_identity = h->identity || (expand && SD == 256);
     h->dev_symbols = SD;
