@@ -389,7 +389,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     uint32_t *mkey = reinterpret_cast<uint32_t *>(lds + a.off_m);
     int32_t *mend = reinterpret_cast<int32_t *>(mkey + MC);
     int32_t *mlab = mend + MC;
-    __shared__ int mn, ovf, sp_n, seg_s, last_s;
+    __shared__ int mn, ovf, sp_n, seg_s, last_s, slice_s;
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
     __shared__ long long ex_s, base_s, segsz_s;
@@ -439,6 +439,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         mn = 0;
         ovf = 0;
         sp_n = 0;
+        slice_s = 0;
     }
     for (int i = ib + tid; i < n16; i += NT) idst[i] = isrc[i];
     if (tid < 256) {
@@ -482,22 +483,27 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
         const int32_t n32 = c.n32;
         const int64_t own_lo = seg_lo + dsh, own_hi = seg_hi + dsh;
         const int64_t s0 = own_lo & ~(int64_t)15;
-        // The wave's slice: a multiple of 16 bytes per wave, owning the
-        // starts of [max(sl, own_lo), sh).
-        const int64_t per = ((own_hi - s0 + 16 * kDfaWaves - 1) / (16 * kDfaWaves)) * 16;
-        int64_t sl = s0 + per * wv;
-        const int64_t sh = sl + per < own_hi ? sl + per : own_hi;
-        if (sl > own_hi) sl = own_hi;
+        const long long m_before = c.M, t_before = c.T, x_before = c.X;
+        c.seg_lo = own_lo;
+        // Waves take the segment's slices (one window each) from a counter,
+        // so a wave held by a long walk does not hold the others' work.
+        const int n_sl = (int)((own_hi - s0 + WIN - 1) / WIN);
+        for (;;) {
+        int k_sl = 0;
+        if (lane == 0) k_sl = atomicAdd(&slice_s, 1);
+        k_sl = __shfl(k_sl, 0);
+        if (k_sl >= n_sl) break;
+        // The slice owns the starts of [max(sl, own_lo), sh).
+        const int64_t sl = s0 + (int64_t)WIN * k_sl;
+        const int64_t sh = sl + WIN < own_hi ? sl + WIN : own_hi;
         auto fetch = [&](int64_t wb) __attribute__((always_inline)) {
             const int64_t p = wb + 16 * lane;
             return p < c.nP ? load_granule(c.xa, p) : make_uint4(0, 0, 0, 0);
         };
         uint4 cur = sl < sh ? fetch(sl) : make_uint4(0, 0, 0, 0);
         uint4 nxt = sl < sh && sl + WIN < c.nP ? fetch(sl + WIN) : make_uint4(0, 0, 0, 0);
-        c.seg_lo = own_lo;
         c.sl = sl;
         c.sl32 = (int32_t)sl;
-        const long long m_before = c.M, t_before = c.T, x_before = c.X;
         if (sl < sh) *reinterpret_cast<uint4 *>(ring + 16 * lane) = cur;
 
         for (int64_t wb = sl; wb < sh; wb += WIN) {
@@ -585,8 +591,10 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             }
             cur = after;
         }
-        // The slice's walks run to their end, then the parked ones.
+        // The slice's walks run to their end (the parked ones after all
+        // slices).
         while (qcount > 0) drain_round<false>(c, q, qcount);
+        }
         __syncthreads();
         const int n_sp = ovf ? 0 : sp_n;
         for (int e0 = 64 * wv; e0 < n_sp; e0 += NT) {
@@ -698,6 +706,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             mn = 0;
             ovf = 0;
             sp_n = 0;
+            slice_s = 0;
         }
         __syncthreads();
     }
