@@ -41,7 +41,7 @@ def parse():
                          "log: line-bounded log search with tag-merged stepping (profiling runs)")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--latency-iters", type=int, default=2000)
+    ap.add_argument("--latency-iters", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-long", action="store_true", help="skip the long-walk (tag-merged vs per-start) measurement")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming (pieces vs whole) measurement")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner report")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-scan (cfg1) latency")
     return ap.parse_args()
 
 
@@ -327,23 +328,68 @@ def autotune():
     return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep.items()}
 
 
-def cpu_baseline(wl, seconds: float):
-    """The oracle as it is, on the host cores, over repeated passes of the
-    same 16 MiB input until `seconds` of wall time have been spent."""
-    import oracle
-    threads = oracle.default_threads()
-    oracle.scan(wl.automaton, wl.data[:1 << 16], threads=threads)  # load the library
+def small_latency(iters: int):
+    """Single-scan latency of the 4 KiB random DFA (launch, scan and count
+    read-back of the synchronous call), p50/p99 over `iters` scans."""
+    import torch
+    import workloads as W
+    import paper_1110_1716_amd as P
+    wl = W.cfg1()
+    h = P.pfsm_load(wl.automaton)
+    try:
+        x = torch.from_numpy(wl.data).cuda()
+        m, _ = P.pfsm_scan(h, x)
+        out = torch.empty((m + 1024, 3), dtype=torch.int32, device="cuda")
+        lat = []
+        for _ in range(iters):
+            t0 = time.perf_counter()
+            P.pfsm_scan(h, x, out=out)
+            lat.append(time.perf_counter() - t0)
+    finally:
+        h.free()
+    us = np.array(lat) * 1e6
+    return {"workload": wl.name, "n_bytes": int(wl.data.size), "matches": int(m), "iters": iters,
+            "p50_us": round(float(np.percentile(us, 50)), 2), "p99_us": round(float(np.percentile(us, 99)), 2),
+            "call": "pfsm_scan (synchronous)"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, wl, threads: int, seconds: float):
     reps, t0 = 0, time.perf_counter()
     while True:
         oracle.scan(wl.automaton, wl.data, threads=threads)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= seconds and reps >= 1:
-            break
+        if el >= seconds:
+            return reps, el
+
+
+def cpu_baseline(wl, seconds: float):
+    """The oracle as it is, on the host cores, over repeated passes of the
+    same 16 MiB input until `seconds` of wall time have been spent; then on
+    one thread for a quarter of that time."""
+    import oracle
+    threads = oracle.default_threads()
+    oracle.scan(wl.automaton, wl.data[:1 << 16], threads=threads)  # load the library
+    reps, el = _oracle_rate(oracle, wl, threads, seconds)
+    reps1, el1 = _oracle_rate(oracle, wl, 1, seconds / 4)
     return {"value": round(reps * wl.data.size / el / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{reps} full passes over the 16 MiB input ({reps * wl.data.size} bytes, "
-                      f"{el:.1f} s wall)"}
+                      f"{el:.1f} s wall)",
+            "single_thread": {"value": round(reps1 * wl.data.size / el1 / 1e9, 4), "unit": "GB/s",
+                              "sample": f"{reps1} full passes, {el1:.1f} s wall"},
+            "cpu_model": _cpu_model()}
 
 
 def main():
@@ -461,6 +507,7 @@ def main():
                 ("long_walks", args.no_long, long_walks),
                 ("streamed", args.no_stream, streamed),
                 ("autotune", args.no_tune, autotune),
+                ("latency_cfg1", args.no_small, lambda: small_latency(10000)),
                 ("cpu_baseline", args.no_cpu, lambda: cpu_baseline(wl, args.cpu_seconds))]
     print(f"bench: {args.workload} scan timed", file=sys.stderr, flush=True)
     for key, skip, fn in sections:
