@@ -65,7 +65,7 @@ def mixed_automata():
 
 def stream_for(rng, aut_idx, n):
     if aut_idx in (0, 3):
-        return bytes(rng.choice(list(b"abcd"), n))
+        return bytes(rng.choice(list(b"abcd"), n).astype(np.uint8))
     return rng.integers(0, 256, n, dtype=np.uint8).tobytes()
 
 

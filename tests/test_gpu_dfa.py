@@ -87,7 +87,7 @@ def test_random_small_dfas(P, seed):
     rng = np.random.default_rng(500 + seed)
     d = W.random_dfa(rng, int(rng.integers(1, 40)), int(rng.integers(1, 6)), p_dead=0.3,
                      n_finals=int(rng.integers(1, 5)), max_labels=3, n_labels=5)
-    x = bytes(rng.choice(list(b"abcdefg"), int(rng.integers(1, 20000))))
+    x = bytes(rng.choice(list(b"abcdefg"), int(rng.integers(1, 6000))).astype(np.uint8))
     check(P, d, x)
 
 

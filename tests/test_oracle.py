@@ -107,8 +107,8 @@ def naive_occurrences(hay: bytes, needle: bytes):
 def test_literal_equals_overlapping_search(seed):
     """One literal pattern reports exactly the overlapping occurrences bytes.find finds."""
     rng = np.random.default_rng(seed)
-    needle = bytes(rng.choice(list(b"ab"), int(rng.integers(1, 5))))
-    hay = bytes(rng.choice(list(b"abc"), 3000))
+    needle = bytes(rng.choice(list(b"ab"), int(rng.integers(1, 5))).astype(np.uint8))
+    hay = bytes(rng.choice(list(b"abc"), 3000).astype(np.uint8))
     got = as_list(oracle.scan(W.literal_dfa(needle, 7), hay)[0])
     assert got == [(i, i + len(needle) - 1, 7) for i in naive_occurrences(hay, needle)]
 
@@ -125,7 +125,7 @@ def test_matches_re_fullmatch(pat):
     rng = np.random.default_rng(len(pat))
     fsm = regex_nfa([(pat, 11)])
     for _ in range(8):
-        x = bytes(rng.choice(list(b"abcd"), 40))
+        x = bytes(rng.choice(list(b"abcd"), 40).astype(np.uint8))
         got = as_list(oracle.scan(fsm, x)[0])
         ref = sorted((s, e, 11) for s in range(len(x)) for e in range(s, len(x))
                      if re.fullmatch(pat, x[s:e + 1], re.DOTALL))
@@ -137,7 +137,7 @@ def test_regex_union_matches_re():
     pats = [(REGEXES[i], 100 + i) for i in range(0, len(REGEXES), 2)]
     fsm = regex_nfa(pats)
     rng = np.random.default_rng(5)
-    x = bytes(rng.choice(list(b"abcd"), 60))
+    x = bytes(rng.choice(list(b"abcd"), 60).astype(np.uint8))
     got = as_list(oracle.scan(fsm, x)[0])
     ref = sorted((s, e, lab) for s in range(len(x)) for e in range(s, len(x)) for p, lab in pats
                  if re.fullmatch(p, x[s:e + 1], re.DOTALL))
@@ -162,7 +162,7 @@ def _small_nfa(seed):
 @pytest.mark.parametrize("seed", range(40))
 def test_dfa_vs_brute_force(seed):
     fsm, rng = _small_dfa(seed)
-    x = bytes(rng.choice(list(b"abcd"), int(rng.integers(0, 28))))
+    x = bytes(rng.choice(list(b"abcd"), int(rng.integers(0, 28))).astype(np.uint8))
     ref = brute.matches(fsm, x)
     for prune in (True, False):
         assert as_list(oracle.scan(fsm, x, prune=prune, threads=3)[0]) == ref
@@ -171,7 +171,7 @@ def test_dfa_vs_brute_force(seed):
 @pytest.mark.parametrize("seed", range(40))
 def test_nfa_vs_brute_force(seed):
     fsm, rng = _small_nfa(seed)
-    x = bytes(rng.choice(list(b"abcd"), int(rng.integers(0, 28))))
+    x = bytes(rng.choice(list(b"abcd"), int(rng.integers(0, 28))).astype(np.uint8))
     ref = brute.matches(fsm, x)
     for prune in (True, False):
         for memo in (True, False):
@@ -182,7 +182,7 @@ def test_nfa_vs_brute_force(seed):
 def test_paper_algorithm_vs_brute_force(seed):
     """The tagged four-step algorithm (Section III.B) reaches the plain definition."""
     fsm, rng = _small_nfa(seed)
-    x = bytes(rng.choice(list(b"abc"), 20))
+    x = bytes(rng.choice(list(b"abc"), 20).astype(np.uint8))
     assert sorted(tagset.run(fsm, x)) == brute.matches(fsm, x)
 
 
@@ -194,7 +194,7 @@ def test_nfa_equals_subset_dfa(seed):
     rng = np.random.default_rng(77 + seed)
     fsm = W.random_nfa(rng, 10, list(b"abcd"), n_edges=24, p_eps=0.2, n_finals=3)
     dfa = subset.to_dfa(fsm)
-    x = bytes(rng.choice(list(b"abcde"), 3000))
+    x = bytes(rng.choice(list(b"abcde"), 3000).astype(np.uint8))
     assert np.array_equal(oracle.scan(fsm, x)[0], oracle.scan(dfa, x)[0])
 
 
@@ -206,7 +206,7 @@ def test_union_is_union_of_match_sets():
         p.final_labels = p.final_labels * 0 + 10 * i
     parts.append(W.random_dfa(rng, 5, 3, p_dead=0.3, n_labels=1))
     parts[-1].final_labels = parts[-1].final_labels * 0 + 99
-    x = bytes(rng.choice(list(b"abcd"), 2000))
+    x = bytes(rng.choice(list(b"abcd"), 2000).astype(np.uint8))
     u = compose.union(parts)
     whole = as_set(oracle.scan(u, x)[0])
     assert whole == set().union(*(as_set(oracle.scan(p, x)[0]) for p in parts))
@@ -298,3 +298,53 @@ def test_log_search_equals_definition():
     ends = np.searchsorted(np.array(nl), np.arange(len(x)))
     steps = [(nl[k] if k < len(nl) else len(x) - 1) - s + 1 for s, k in enumerate(ends)]
     assert wk["T"] == sum(steps)
+
+
+# ---------------------------------------------------------------- generated automata
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@st.composite
+def small_dfas(draw):
+    n = draw(st.integers(1, 6))
+    s = draw(st.integers(1, 3))
+    delta = draw(st.lists(st.integers(-1, n - 1), min_size=n * s, max_size=n * s))
+    finals = draw(st.dictionaries(st.integers(0, n - 1), st.lists(st.integers(0, 4), min_size=1, max_size=3),
+                                  max_size=n))
+    off, lab = W.label_csr(n, finals)
+    b2s = -np.ones(256, dtype=np.int16)
+    for k in range(s):
+        b2s[ord("a") + k] = k
+    return W.DFA(n, s, draw(st.integers(0, n - 1)), b2s, np.array(delta, np.int32), off, lab)
+
+
+@st.composite
+def small_nfas(draw):
+    n = draw(st.integers(1, 6))
+    classes = draw(st.lists(st.sets(st.sampled_from(list(b"abc")), min_size=1, max_size=3), min_size=1, max_size=4))
+    edges = draw(st.lists(st.tuples(st.integers(0, n - 1), st.integers(-1, len(classes) - 1), st.integers(0, n - 1)),
+                          max_size=3 * n))
+    finals = draw(st.dictionaries(st.integers(0, n - 1), st.lists(st.integers(0, 4), min_size=1, max_size=3),
+                                  max_size=n))
+    src = [e[0] for e in edges]
+    cls = [e[1] for e in edges]
+    dst = [e[2] for e in edges]
+    return W.build_nfa(n, draw(st.integers(0, n - 1)), src, cls, dst, [sorted(c) for c in classes], finals)
+
+
+@settings(max_examples=150, deadline=None)
+@given(small_dfas(), st.binary(max_size=14).map(lambda b: bytes(ord("a") + c % 4 for c in b)))
+def test_generated_dfas_vs_brute_force(fsm, x):
+    ref = brute.matches(fsm, x)
+    for prune in (True, False):
+        assert as_list(oracle.scan(fsm, x, prune=prune, threads=2)[0]) == ref
+
+
+@settings(max_examples=150, deadline=None)
+@given(small_nfas(), st.binary(max_size=14).map(lambda b: bytes(ord("a") + c % 4 for c in b)))
+def test_generated_nfas_vs_brute_force(fsm, x):
+    ref = brute.matches(fsm, x)
+    for prune in (True, False):
+        for memo in (True, False):
+            assert as_list(oracle.scan(fsm, x, prune=prune, memo=memo, threads=2)[0]) == ref
