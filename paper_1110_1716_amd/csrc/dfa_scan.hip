@@ -1,33 +1,34 @@
 // All-matches DFA scan for gfx950 (Section III.B with a deterministic
 // transition function; the DFA case of Section III.C).
 //
-// Persistent cooperative grid of 768-thread workgroups (12 wave64, one per
-// compute unit when the table is resident in LDS).  Workgroup b owns the
-// start positions of one contiguous segment per round (lazy data
-// partitioning, Section III.D.2: a segment owns its starts, its walks read
-// past its end until they die), and each wave owns a contiguous slice of the
-// segment, which it works through in 1 KiB windows (16 bytes per lane) with
-// no synchronisation between waves:
-//   1. the wave keeps its window and the next one staged in a private 2 KiB
-//      LDS ring, loading the window after next from HBM while it works;
+// An ordinary launch of 768-thread workgroups (12 wave64, one per compute
+// unit when the table is resident in LDS), at most as many as fit at once.
+// Workgroups take segments of the input from a ticket counter; a segment
+// owns its start positions and its walks read past its end until they die
+// (lazy data partitioning, Section III.D.2).  Within a segment the waves
+// take 1 KiB slices (16 bytes per lane) from an LDS counter, with no other
+// synchronisation between waves:
+//   1. the wave stages its slice and the next 1 KiB in a private 2 KiB LDS
+//      ring;
 //   2. every start takes its first symbol through a byte-indexed liveness
 //      table of q0's row (Section III.B steps 1-4 for the fresh tag), 16
 //      independent lookups per lane; the starts that survive are compacted
-//      (ballot prefix) into a list and take their second symbol through the
-//      table (resident in LDS, or the LDS copies of q0's successor rows)
-//      with every lane busy;
-//   3. walks still live go to a wave-private LDS queue and advance in rounds
-//      of up to 16 symbols while their bytes are staged; a walk that reaches
-//      the end of the staged pair waits for the next window, and the ones
-//      alive at the end of the slice finish reading through L2;
+//      (ballot prefix) into a list and walk on through the table (resident
+//      in LDS, or the LDS copies of q0's successor rows) with every lane
+//      busy, one LDS round trip per step;
+//   3. a walk that reaches the end of the staged pair waits in a
+//      wave-private LDS queue, and the queued walks finish at the end of
+//      the slice, reading through L2 in 16-byte chunks;
 //   4. every final state entered adds (start, end, label) to an LDS buffer
 //      under the key (start - segment start, k), k = the instance's match
 //      count so far, which orders (end, label) within a start (Section III.B
 //      reporting rule).
-// At the end of a round each workgroup publishes its match count in its own
-// epoch-tagged slot and sums its peers' slots (no shared counters), then
-// writes every buffered match at its rank.  A segment whose matches do not
-// fit the buffer is re-walked 768 starts at a time: count, scan, write.
+// At the end of a segment the workgroup finds its output offset by
+// decoupled look-back over earlier tickets (a predecessor holds an earlier
+// ticket, so it is already running) and writes every buffered match at its
+// rank.  A segment whose matches do not fit the buffer, or whose parked
+// walks outgrow the spill area, is re-walked 768 starts at a time: count,
+// scan, write.
 #include "scan_common.h"
 #include "stream.h"
 
@@ -500,19 +501,17 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             const int64_t p = wb + 16 * lane;
             return p < c.nP ? load_granule(c.xa, p) : make_uint4(0, 0, 0, 0);
         };
-        uint4 cur = sl < sh ? fetch(sl) : make_uint4(0, 0, 0, 0);
-        uint4 nxt = sl < sh && sl + WIN < c.nP ? fetch(sl + WIN) : make_uint4(0, 0, 0, 0);
+        // The slice and the next 1 KiB are staged; walks still live at the
+        // end of the pair wait in the queue (empty when a slice begins).
+        const uint4 cur = fetch(sl);
+        const uint4 nxt = sl + WIN < c.nP ? fetch(sl + WIN) : make_uint4(0, 0, 0, 0);
         c.sl = sl;
         c.sl32 = (int32_t)sl;
-        if (sl < sh) *reinterpret_cast<uint4 *>(ring + 16 * lane) = cur;
-
-        for (int64_t wb = sl; wb < sh; wb += WIN) {
-            // Stage the next window beside this one and request the one after.
-            const int rb = (int)((wb - sl) & (RING - 1));
-            *reinterpret_cast<uint4 *>(ring + ((rb + WIN) & (RING - 1)) + 16 * lane) = nxt;
-            const uint4 after = nxt;
-            if (wb + WIN < sh && wb + 2 * WIN < c.nP) nxt = fetch(wb + 2 * WIN);
-            __builtin_amdgcn_wave_barrier();
+        *reinterpret_cast<uint4 *>(ring + 16 * lane) = cur;
+        *reinterpret_cast<uint4 *>(ring + WIN + 16 * lane) = nxt;
+        __builtin_amdgcn_wave_barrier();
+        {
+            const int64_t wb = sl;
             c.wbase = wb;
             const int64_t rest = c.nP - wb;
             c.staged = (int)(rest < RING ? rest : RING);
@@ -520,27 +519,11 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
             // The staged pair ends at lim.
             const int32_t lim = (int32_t)(rest < RING ? c.nP : wb + RING);
 
-            // Walks parked at the end of the previous window continue.
-            {
-                const int n_old = qcount;
-                qcount = 0;
-                for (int e0 = 0; e0 < n_old; e0 += 64) {
-                    const int e = e0 + lane;
-                    const bool act = e < n_old;
-                    QEnt w = act ? q[e] : QEnt{0, 0, 0, 0};
-                    __builtin_amdgcn_wave_barrier();
-                    const bool park = advance_staged(c, act, w.start, w.state, w.pos, w.k, lim);
-                    const int slot = wave_push_slot(qcount, park);
-                    if (park) q[slot] = w;
-                    __builtin_amdgcn_wave_barrier();
-                }
-            }
-
             // Starts owned by this lane: its 16 bytes within [own_lo, sh).
-            const int64_t lb = wb + 16 * lane;
-            const int64_t hi64 = sh - lb, lo64 = own_lo - lb;
-            const int khi = hi64 <= 0 ? 0 : (hi64 >= 16 ? 16 : (int)hi64);
-            const int klo = lo64 <= 0 ? 0 : (lo64 >= 16 ? 16 : (int)lo64);
+            // (sh - wb and own_lo - wb lie within one segment of each other)
+            const int rhi = (int)(sh - wb) - 16 * lane, rlo = (int)(own_lo - wb) - 16 * lane;
+            const int khi = rhi <= 0 ? 0 : (rhi >= 16 ? 16 : rhi);
+            const int klo = rlo <= 0 ? 0 : (rlo >= 16 ? 16 : rlo);
             const unsigned vmask = ((1u << khi) - 1u) & ~((1u << klo) - 1u);
             c.T += __popc(vmask);
 #pragma unroll
@@ -589,9 +572,8 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-            cur = after;
         }
-        // The slice's walks run to their end (the parked ones after all
+        // The slice's walks run to their end (the spilled ones after all
         // slices).
         while (qcount > 0) drain_round<false>(c, q, qcount);
         }

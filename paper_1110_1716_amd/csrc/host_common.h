@@ -93,8 +93,8 @@ struct Workspace {
     int lb_cap = 0;
     void *spill = nullptr;                // DFA: [n_blocks * kDfaSpill] walks
     long long *bstats = nullptr;          // [n_blocks * 4]
-    int64_t *d_total = nullptr;
-    int64_t *h_total = nullptr;           // pinned
+    int64_t *h_total = nullptr;           // pinned, mapped
+    int64_t *h_total_dev = nullptr;       // h_total's device address
     long long *h_stats = nullptr;         // pinned [n_blocks * 4]
     bool scanned = false;
     uint64_t used = 0;                    // launch sequence number of the last scan
@@ -113,7 +113,6 @@ struct Workspace {
         if (lb) (void)hipFree(lb);
         if (spill) (void)hipFree(spill);
         if (bstats) (void)hipFree(bstats);
-        if (d_total) (void)hipFree(d_total);
         if (h_total) (void)hipHostFree(h_total);
         if (h_stats) (void)hipHostFree(h_stats);
         if (stage) (void)hipFree(stage);
@@ -156,8 +155,10 @@ struct WorkspacePool {
         HIP_TRY(hipMemset(w->lb, 0, sizeof(unsigned long long) * w->lb_cap));
         HIP_TRY(hipMalloc(&w->bstats, sizeof(long long) * 4 * n_blocks));
         HIP_TRY(hipMemset(w->bstats, 0, sizeof(long long) * 4 * n_blocks));
-        HIP_TRY(hipMalloc(&w->d_total, sizeof(int64_t)));
-        HIP_TRY(hipHostMalloc(&w->h_total, sizeof(int64_t), hipHostMallocDefault));
+        // The synchronous scan's kernels store the total straight into this
+        // mapped, coherent host word: no copy is queued behind the scan.
+        HIP_TRY(hipHostMalloc(&w->h_total, sizeof(int64_t), hipHostMallocMapped | hipHostMallocCoherent));
+        HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void **>(&w->h_total_dev), w->h_total, 0));
         HIP_TRY(hipHostMalloc(&w->h_stats, sizeof(long long) * 4 * n_blocks, hipHostMallocDefault));
         HIP_TRY(hipDeviceSynchronize());
         *out = w.get();
@@ -241,10 +242,20 @@ inline int grid_blocks(int occ, int cus, int wpc) {
 
 // Split n bytes over a persistent grid of n_blocks workgroups: bytes per
 // workgroup and round (a multiple of 16) and the number of rounds.
-inline void plan_segments(int64_t n, int n_blocks, int64_t seg_target, int64_t *seg, int *rounds) {
+// Segments are n / n_blocks bytes, at least seg_floor and at most
+// seg_target (a multiple of 16).  Small DFA inputs use a 4 KiB floor (four
+// slices): below it a segment's fixed work (start-up, ticket, look-back)
+// outweighs its walks, which run one start per lane.  NFA inputs keep
+// 16-byte segments, because a start whose state set outgrows a lane is
+// replayed by its whole workgroup, one start at a time, so starts spread
+// over more workgroups replay in parallel.
+constexpr int64_t kDfaSegFloor = 4096;
+constexpr int64_t kNfaSegFloor = 16;
+
+inline void plan_segments(int64_t n, int n_blocks, int64_t seg_target, int64_t seg_floor, int64_t *seg, int *rounds) {
     int64_t per = (n + n_blocks - 1) / n_blocks;
     per = (per + 15) / 16 * 16;
-    if (per < 16) per = 16;
+    if (per < seg_floor) per = seg_floor;
     if (per > seg_target) per = seg_target;
     *seg = per;
     *rounds = (int)((n + per * n_blocks - 1) / (per * n_blocks));

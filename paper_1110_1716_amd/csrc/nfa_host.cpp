@@ -532,7 +532,8 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
         a.seg = seg;
     } else {
         int rounds;
-        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kNfaSegMax, &a.seg, &rounds);
+        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kNfaSegMax, kNfaSegFloor, &a.seg,
+                      &rounds);
         const int64_t n_segs = (n + a.seg - 1) / a.seg;
         if ((rc = grow_lb(w, (int)n_segs))) return rc;
         a.n_segs = (int32_t)n_segs;

@@ -606,8 +606,24 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
             walk_block(c, bg.start, bg.k0, bg.pos0, kBuffer, 0, F0, F1, bits, sh);
         }
         __syncthreads();
-        if (tid == 0) nbig = 0;
+        // Starts dropped from a full list are walked by nobody: the segment
+        // is then recounted and rewritten from per-start walks.
+        if (tid == 0) {
+            if (nbig > BC) ovf = 1;
+            nbig = 0;
+        }
         __syncthreads();
+    };
+    // Replay the listed starts once the list is half full (a uniform
+    // decision taken at the end of each window).
+    auto replay_if_full = [&](int &qcount) __attribute__((always_inline)) {
+        __syncthreads();
+        const int pending = nbig;
+        __syncthreads();
+        if (pending > BC / 2) {
+            while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig);
+            run_big();
+        }
     };
 
     for (;;) {
@@ -717,14 +733,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-            // replay list getting full: run it now (uniform decision)
-            __syncthreads();
-            const int pending = nbig;
-            __syncthreads();
-            if (pending > BC / 2) {
-                while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig);
-                run_big();
-            }
+            replay_if_full(qcount);
         }
         while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig);
         __syncthreads();

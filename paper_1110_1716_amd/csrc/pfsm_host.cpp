@@ -465,7 +465,8 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
         a.seg = seg;
     } else {
         int rounds;
-        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax, &a.seg, &rounds);
+        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax, kDfaSegFloor, &a.seg,
+                      &rounds);
         const int64_t n_segs = (n + a.seg - 1) / a.seg;
         if ((rc = grow_lb(w, (int)n_segs))) return rc;
         a.n_segs = (int32_t)n_segs;
@@ -567,11 +568,10 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
     const int nb = h->kind == 1 ? nfa_grid_blocks(h->nfa.get()) : h->n_blocks;
     int rc = (h->kind == 1 ? nfa_pool(h->nfa.get()) : &h->pool)->get(s, nb, &w);
     if (rc) return rc;
-    rc = pfsm_scan_async(h, d_input, n, d_out, cap, w->d_total, hip_stream);
+    rc = pfsm_scan_async(h, d_input, n, d_out, cap, w->h_total_dev, hip_stream);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(w->h_total, w->d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    *n_matches = *w->h_total;
+    *n_matches = *reinterpret_cast<volatile int64_t *>(w->h_total);
     if (*n_matches > cap)
         return fail(PFSM_EOVERFLOW, "%lld matches, capacity %lld", (long long)*n_matches, (long long)cap);
     return PFSM_OK;

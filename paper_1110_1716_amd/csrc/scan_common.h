@@ -13,23 +13,27 @@ __device__ __forceinline__ unsigned long long lanes_below() {
     return (1ull << lane_id()) - 1ull;
 }
 
+// Set bits of m in the lanes below this one (two mbcnt instructions).
+__device__ __forceinline__ int lanes_below_count(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 // Reserve one slot per lane with `pred` in a wave-private LDS queue whose
 // count lives in a wave-uniform register.  Returns the slot or -1.
 __device__ __forceinline__ int wave_push_slot(int &count, bool pred) {
     const unsigned long long m = __ballot(pred);
-    const int slot = count + __popcll(m & lanes_below());
+    const int slot = count + lanes_below_count(m);
     count += __popcll(m);
     return pred ? slot : -1;
 }
 
 // Exclusive prefix over the wave of a count in [0, 16), and the wave total.
 __device__ __forceinline__ int wave_excl_small(int v, int &total) {
-    const unsigned long long below = lanes_below();
     int ex = 0, tot = 0;
 #pragma unroll
     for (int bit = 0; bit < 4; ++bit) {
         const unsigned long long m = __ballot((v >> bit) & 1);
-        ex += __popcll(m & below) << bit;
+        ex += lanes_below_count(m) << bit;
         tot += __popcll(m) << bit;
     }
     total = tot;

@@ -202,3 +202,25 @@ def test_replay_list_overflow_recounted(P):
         assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
     finally:
         h.free()
+
+
+@pytest.mark.parametrize("pat", [b"a.{0,3}b", b"(ab|cd)+", b"a(b|c)*d"])
+def test_replay_list_overflow_mid_segment(P, pat):
+    # one full 4 KiB window per segment, four waves listing replays at once:
+    # the list overflows before its first run while the matches still fit
+    # the buffer, so only the dropped replays can force the recount
+    rng = np.random.default_rng(len(pat))
+    x = rng.choice(list(b"abcd"), 3000).astype(np.uint8)
+    fsm = regex_nfa([(pat, 3)])
+    ref, wk = oracle.scan(fsm, x)
+    assert len(ref) < 1024
+    h = P.pfsm_load(fsm)
+    try:
+        for seg in (4096, 65536):
+            P.pfsm_set_option(h, P.PFSM_OPT_SEGMENT, seg)
+            n, out = P.pfsm_scan(h, dev(x))
+            assert np.array_equal(out.cpu().numpy(), ref), seg
+            st = P.pfsm_last_stats(h)
+            assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref)), seg
+    finally:
+        h.free()
