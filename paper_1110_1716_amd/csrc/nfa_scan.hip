@@ -473,7 +473,9 @@ __device__ __forceinline__ long long walk_block(Ctx &c, int32_t s, int32_t k0, i
 
 // One queue round of this wave: every walk advances through the rest of the
 // 16-byte chunk holding its next position.  Walks whose set outgrows K go to
-// the workgroup's replay list.
+// the workgroup's replay list.  A lane's walks advance together, one symbol
+// each per step, and the state records of all of them are requested before
+// any is used, so their L2 round trips overlap.
 template <class Ctx>
 __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *big_s, int *nbig) {
     const NfaArgs &a = c.a;
@@ -488,21 +490,44 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
         else e[j].n = 0;
     }
     __builtin_amdgcn_wave_barrier();
+    uint4 ch[QK];
+    int steps[QK];
 #pragma unroll
     for (int j = 0; j < QK; ++j) {
-        if (!alive[j]) continue;
-        const int64_t c0 = (int64_t)(e[j].pos & ~15);
-        const uint4 ch = load_granule(c.xa, c0);
-        ++c.L;
-        const int steps = (int)((c0 + 16 < c.nP ? c0 + 16 : c.nP) - e[j].pos);
-        for (int st = 0; st < steps && alive[j]; ++st) {
+        steps[j] = 0;
+        ch[j] = make_uint4(0, 0, 0, 0);
+        if (alive[j]) {
+            const int64_t c0 = (int64_t)(e[j].pos & ~15);
+            ch[j] = load_granule(c.xa, c0);
+            ++c.L;
+            steps[j] = (int)((c0 + 16 < c.nP ? c0 + 16 : c.nP) - e[j].pos);
+        }
+    }
+    for (int st = 0; st < 16; ++st) {
+        bool act[QK];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < QK; ++j) {
+            act[j] = alive[j] && st < steps[j];
+            any |= act[j];
+        }
+        if (!__any(any)) break;
+        NfaRec r[QK][K];
+#pragma unroll
+        for (int j = 0; j < QK; ++j)
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if (act[j] && t < e[j].n) r[j][t] = a.rec[e[j].s[t] & kStateMask];
+#pragma unroll
+        for (int j = 0; j < QK; ++j) {
+            if (!act[j]) continue;
             uint32_t O[K];
             int nO;
-            if (!nfa_step(a, e[j].s, e[j].n, byte_of(ch, e[j].pos & 15), O, nO)) {
+            if (!nfa_step_rec(a, r[j], e[j].n, byte_of(ch[j], e[j].pos & 15), O, nO)) {
                 const int slot = atomicAdd(nbig, 1);
                 if (slot < BC) big_s[slot] = Big{e[j].start, e[j].k, e[j].pos, 0};
                 alive[j] = false;
-                break;
+                continue;
             }
             ++c.T;
             c.X += nO;
