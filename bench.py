@@ -4,7 +4,10 @@ A step is one full scan (every start position, every match written in
 (start, end, label) order) of one 16 MiB input against a resident 256-state
 byte DFA: the random-DFA workload with planted accepting walks.  Inputs are
 resident in HBM before timing starts and rotate through 64 distinct copies
-(1 GiB), so that the 256 MB Infinity Cache cannot serve them.
+(1 GiB), so that the 256 MB Infinity Cache cannot serve them.  The K timed
+scans run back to back, replayed from HIP graphs (one scan per input copy),
+with events around the timed region; --eager launches them one by one with
+events around each instead.
 
 Prints one JSON line with GB/s (value), transitions/s, the single-scan
 latency distribution of the synchronous call, the roofline position of the
@@ -42,6 +45,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--latency-iters", type=int, default=10000)
+    ap.add_argument("--eager", action="store_true",
+                    help="time one launch per scan with events around each, instead of HIP-graph replays")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -427,8 +432,9 @@ def main():
         torch.cuda.synchronize()
         del a_, b_
 
-    # reference count and work counters of one scan (from the kernel's own counters)
-    n_ref, _ = P.pfsm_scan(h, xs[0], out=out)
+    # reference result and work counters of one scan (from the kernel's own counters)
+    n_ref, ref_rows = P.pfsm_scan(h, xs[0], out=out)
+    ref_rows = ref_rows.cpu().numpy().copy()
     stats = P.pfsm_last_stats(h)
     transitions = stats["transitions"]
 
@@ -436,24 +442,67 @@ def main():
         P.pfsm_scan_async(h, xs[i % n_copies], out, counts[i:i + 1])
     torch.cuda.synchronize()
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    for i in range(args.steps):
-        k = args.warmup + i
-        ev[i][0].record(stream)
-        P.pfsm_scan_async(h, xs[k % n_copies], out, counts[k:k + 1])
-        ev[i][1].record(stream)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    total_ms = t_start.elapsed_time(t_end)
-    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    got = counts.cpu().numpy()
+    if args.eager:
+        # one launch per scan, events around each
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t_start.record(stream)
+        for i in range(args.steps):
+            k = args.warmup + i
+            ev[i][0].record(stream)
+            P.pfsm_scan_async(h, xs[k % n_copies], out, counts[k:k + 1])
+            ev[i][1].record(stream)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        total_ms = t_start.elapsed_time(t_end)
+        kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+        got = counts.cpu().numpy()
+        timing = "one launch per scan; events around each launch"
+    else:
+        # K back-to-back scans replayed from HIP graphs: one graph of a scan
+        # per resident input copy, replayed K // copies times, and one of the
+        # remaining K % copies scans; events around the whole region
+        gs = torch.cuda.Stream()
+        gs.wait_stream(stream)
+        with torch.cuda.stream(gs):
+            for i in range(2):
+                P.pfsm_scan_async(h, xs[i % n_copies], out, counts[i:i + 1], stream=gs)
+        gs.synchronize()
+        cnt_g = torch.zeros(n_copies, dtype=torch.int64, device=dev)
+        reps, rest = divmod(args.steps, n_copies)
+        graphs = []
+        for m in ([n_copies] if reps else []) + ([rest] if rest else []):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=gs):
+                for k in range(m):
+                    P.pfsm_scan_async(h, xs[k], out, cnt_g[k:k + 1], stream=gs)
+            graphs.append((g, m))
+        with torch.cuda.stream(gs):
+            for g, _ in graphs:
+                g.replay()  # untimed
+        gs.synchronize()
+        wall0 = time.perf_counter()
+        with torch.cuda.stream(gs):
+            t_start.record(gs)
+            for _ in range(reps):
+                graphs[0][0].replay()
+            if rest:
+                graphs[-1][0].replay()
+            t_end.record(gs)
+        gs.synchronize()
+        wall = time.perf_counter() - wall0
+        total_ms = t_start.elapsed_time(t_end)
+        kern_ms = np.array([total_ms / args.steps])
+        got = cnt_g[:min(args.steps, n_copies)].cpu().numpy()
+        last = out[:n_ref].cpu().numpy()
+        if not np.array_equal(last, ref_rows):
+            raise SystemExit("the graph-replayed scan's matches differ from the eager scan's")
+        timing = "HIP-graph replays of back-to-back scans; events around the timed region"
     if not np.all(got == n_ref):
         raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
 
@@ -500,6 +549,7 @@ def main():
                      "kernel": kernel, "kernel_avg_us": round(kern_avg_s * 1e6, 3),
                      "alg_bytes_per_launch": int(alg_bytes)},
         "wall_s_timed": round(wall, 4),
+        "timing": timing,
     }
     h.free()
     sections = [("batched", args.no_batch, lambda: batched_vs_plain(args.batch_replays)),
