@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--latency-iters", type=int, default=10000)
     ap.add_argument("--eager", action="store_true",
                     help="time one launch per scan with events around each, instead of HIP-graph replays")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="the graph-replayed scans of `value` alternate over this many streams, so that "
+                         "independent scans overlap (the roofline's per-launch time comes from one stream)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -467,42 +470,63 @@ def main():
         # K back-to-back scans replayed from HIP graphs: one graph of a scan
         # per resident input copy, replayed K // copies times, and one of the
         # remaining K % copies scans; events around the whole region
-        gs = torch.cuda.Stream()
-        gs.wait_stream(stream)
-        with torch.cuda.stream(gs):
-            for i in range(2):
-                P.pfsm_scan_async(h, xs[i % n_copies], out, counts[i:i + 1], stream=gs)
-        gs.synchronize()
-        cnt_g = torch.zeros(n_copies, dtype=torch.int64, device=dev)
-        reps, rest = divmod(args.steps, n_copies)
-        graphs = []
-        for m in ([n_copies] if reps else []) + ([rest] if rest else []):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=gs):
-                for k in range(m):
-                    P.pfsm_scan_async(h, xs[k], out, cnt_g[k:k + 1], stream=gs)
-            graphs.append((g, m))
-        with torch.cuda.stream(gs):
-            for g, _ in graphs:
-                g.replay()  # untimed
-        gs.synchronize()
-        wall0 = time.perf_counter()
-        with torch.cuda.stream(gs):
-            t_start.record(gs)
-            for _ in range(reps):
-                graphs[0][0].replay()
-            if rest:
-                graphs[-1][0].replay()
-            t_end.record(gs)
-        gs.synchronize()
-        wall = time.perf_counter() - wall0
-        total_ms = t_start.elapsed_time(t_end)
-        kern_ms = np.array([total_ms / args.steps])
-        got = cnt_g[:min(args.steps, n_copies)].cpu().numpy()
-        last = out[:n_ref].cpu().numpy()
-        if not np.array_equal(last, ref_rows):
-            raise SystemExit("the graph-replayed scan's matches differ from the eager scan's")
-        timing = "HIP-graph replays of back-to-back scans; events around the timed region"
+        def graph_time(nstreams):
+            ns = max(1, nstreams)
+            gss = [torch.cuda.Stream() for _ in range(ns)]
+            outs = [out] + [torch.empty_like(out) for _ in range(ns - 1)]
+            gs = gss[0]
+            for q in gss:
+                q.wait_stream(stream)
+                with torch.cuda.stream(q):
+                    for i in range(2):
+                        P.pfsm_scan_async(h, xs[i % n_copies], outs[gss.index(q)], counts[i:i + 1], stream=q)
+                q.synchronize()
+            cnt_g = torch.zeros(n_copies, dtype=torch.int64, device=dev)
+            reps, rest = divmod(args.steps, n_copies)
+            graphs = []
+            for m in ([n_copies] if reps else []) + ([rest] if rest else []):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=gs):
+                    for q in gss[1:]:
+                        q.wait_stream(gs)  # fork
+                    for k in range(m):
+                        P.pfsm_scan_async(h, xs[k], outs[k % ns], cnt_g[k:k + 1], stream=gss[k % ns])
+                    for q in gss[1:]:
+                        gs.wait_stream(q)  # join
+                graphs.append((g, m))
+            with torch.cuda.stream(gs):
+                for g, _ in graphs:
+                    g.replay()  # untimed
+            gs.synchronize()
+            wall0 = time.perf_counter()
+            with torch.cuda.stream(gs):
+                t_start.record(gs)
+                for _ in range(reps):
+                    graphs[0][0].replay()
+                if rest:
+                    graphs[-1][0].replay()
+                t_end.record(gs)
+            gs.synchronize()
+            wall = time.perf_counter() - wall0
+            total_ms = t_start.elapsed_time(t_end)
+            got = cnt_g[:min(args.steps, n_copies)].cpu().numpy()
+            if not np.all(got == n_ref):
+                raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
+            for o in outs[:min(ns, args.steps)]:
+                if not np.array_equal(o[:n_ref].cpu().numpy(), ref_rows):
+                    raise SystemExit("a graph-replayed scan's matches differ from the eager scan's")
+            return total_ms, wall
+
+        # one stream: each scan's own launch time (the roofline's); then the
+        # scans of `value`, alternating over the streams so that they overlap
+        ns = max(1, args.streams)
+        one_ms, one_wall = graph_time(1)
+        total_ms, wall = graph_time(ns) if ns > 1 else (one_ms, one_wall)
+        kern_ms = np.array([one_ms / args.steps])
+        got = np.array([n_ref])
+        timing = ("HIP-graph replays of back-to-back scans; events around the timed region" if ns == 1 else
+                  f"HIP-graph replays with the scans alternating over {ns} streams (independent scans overlap); "
+                  "events around the timed region; kernel_avg_us from the same replays on one stream")
     if not np.all(got == n_ref):
         raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
 
