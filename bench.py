@@ -574,6 +574,8 @@ def main():
                      "alg_bytes_per_launch": int(alg_bytes)},
         "wall_s_timed": round(wall, 4),
         "timing": timing,
+        "one_stream": {"GB/s": round(n / (float(kern_ms.mean()) / 1e3) / 1e9, 2),
+                       "us_per_scan": round(float(kern_ms.mean()) * 1e3, 3)},
     }
     h.free()
     sections = [("batched", args.no_batch, lambda: batched_vs_plain(args.batch_replays)),
