@@ -16,7 +16,8 @@
 //     duplicate-free, so every state is expanded once per symbol) and wait in
 //     a wave-private LDS queue; each queue round advances every walk through
 //     the rest of a 16-byte input chunk, one packed 32-byte state record load
-//     per state and symbol.
+//     per state and symbol.  A lane holds two walks, which step together so
+//     that their record loads overlap.
 //   * An instance whose set outgrows kNfaK is replayed by the whole workgroup
 //     from its start: frontier lists and a visited bitset in global scratch,
 //     the matches it had already reported skipped.
@@ -35,7 +36,7 @@ namespace {
 
 constexpr int NT = kNfaThreads;
 constexpr int W = kNfaWindow;
-constexpr int K = 4;  // states a queued walk keeps
+constexpr int K = kNfaK;  // states a queued walk keeps
 constexpr int QW = kNfaQueue * 2;
 constexpr int QK = QW / 64;
 constexpr int MC = kNfaMatchCap;

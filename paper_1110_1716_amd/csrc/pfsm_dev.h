@@ -191,7 +191,7 @@ namespace pfsmk {
 constexpr int kNfaThreads = 256;             // workgroup: 4 wave64
 constexpr int kNfaWindow = kNfaThreads * 16; // 16 starts per thread
 constexpr int kNfaSegMax = 65536;            // bytes per workgroup and round
-constexpr int kNfaK = 8;                     // states a lane keeps for one walk
+constexpr int kNfaK = 4;                     // states a queued walk keeps in registers
 constexpr int kNfaQueue = 64;                // walk queue entries per wave
 constexpr int kNfaMatchCap = 1024;           // LDS match buffer per workgroup
 constexpr int kNfaBigCap = 256;              // replayed starts listed per workgroup
