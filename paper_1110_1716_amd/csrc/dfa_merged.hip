@@ -215,6 +215,9 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
                             M += (long long)L * sz;
                             for (int g = head; g >= 0; g = nxt[g]) kc[g] += L;
                         } else {
+                            // (the first label is read once: the output
+                            // stores would otherwise force a reload per tag)
+                            const int32_t lab0 = L > 0 ? a.lab[l0] : 0;
                             for (int g = head; g >= 0; g = nxt[g]) {
                                 const long long k = kc[g];
                                 for (int l = 0; l < L; ++l) {
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
                                         MatchOut *o = &a.out[at];
                                         o->start = (int32_t)(lo + g);
                                         o->end = (int32_t)p;
-                                        o->label = a.lab[l0 + l];
+                                        o->label = l == 0 ? lab0 : a.lab[l0 + l];
                                     }
                                 }
                                 kc[g] = k + L;
