@@ -223,10 +223,14 @@ enum {
                                          when they fit (default), 0 = never                        */
     PFSM_OPT_MAX_WORKGROUPS_PER_CU = 5, /* read only: how many workgroups fit per compute unit      */
     PFSM_OPT_RESIDENT_TABLE = 6,      /* read only, DFA: 1 when the table is resident in LDS        */
-    PFSM_OPT_MERGED_WALKS = 7         /* DFA with at most 63 states: 1 = tag-merged stepping (one
+    PFSM_OPT_MERGED_WALKS = 7,        /* DFA with at most 63 states: 1 = tag-merged stepping (one
                                          lookup per distinct active state, Section III.B) for single
                                          scans; 0 = one walk per start (default).  Batches and
                                          streams always walk per start.                            */
+    PFSM_OPT_MERGED_COUNT_LIMIT = 8   /* tag-merged stepping keeps per-start match counts and
+                                         output offsets in 32 bits up to this value, and larger
+                                         ones in 64 bits in memory: 0 = 2^31 - 1 (default); a small
+                                         value exercises the memory paths (results are the same)  */
 };
 
 /* Set a writable option (table budget and pair cache rebuild the device

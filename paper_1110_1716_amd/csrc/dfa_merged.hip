@@ -47,7 +47,12 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
     extern __shared__ __align__(16) uint8_t tab_s[];
     __shared__ int32_t laboff_s[kMergedStates + 1];
     __shared__ int16_t next_s[MW][SEG];   // tag list links (-1: end)
-    __shared__ long long kc_s[MW][SEG];   // matches per tag, then output offsets
+    // matches per tag, then output offsets, in 32 bits up to a.narrow_max;
+    // counts that would pass it continue in 64 bits in a.tag_cnt (spill_s
+    // marks those tags), and a segment whose total passes it keeps its
+    // offsets there
+    __shared__ int32_t kc_s[MW][SEG];
+    __shared__ unsigned long long spill_s[MW][SEG / 64];
     __shared__ uint8_t stage_s[MW][WIN];
     __shared__ int32_t own_s[MW][64], tail_s[MW][64], size_s[MW][64];
     __shared__ long long red4[4 * MW];
@@ -65,7 +70,9 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
     const uint8_t *xa = a.x - dsh;
     const int64_t nP = a.n + dsh;
     int16_t *nxt = next_s[wv];
-    long long *kc = kc_s[wv];
+    int32_t *kc = kc_s[wv];
+    unsigned long long *spill = spill_s[wv];
+    const int lim = a.narrow_max;
     uint8_t *stage = stage_s[wv];
     int32_t *own = own_s[wv];
     int32_t *tailw = tail_s[wv];
@@ -86,27 +93,31 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
         const int64_t hi = lo + SEG < a.n ? lo + SEG : a.n;
         const int pass = a.pass;
         long long base = 0;
+        bool wide = false;  // offsets kept in a.tag_cnt (64 bits)
         if (pass == 0) {
             for (int g = lane; g < SEG; g += 64) kc[g] = 0;
+            if (lane < SEG / 64) spill[lane] = 0;
         } else {
             // this segment's starts: output offsets from their counts
             base = a.seg_base[sg];
             if (a.seg_base[sg + 1] == base) continue;  // no matches
+            wide = a.seg_base[sg + 1] - base > lim;
             constexpr int PER = SEG / 64;
             long long own_sum = 0;
             for (int j = 0; j < PER; ++j) {
                 const int64_t i = lo + lane * PER + j;
-                const long long c = i < hi ? a.tag_cnt[i] : 0;
-                kc[lane * PER + j] = c;
-                own_sum += c;
+                own_sum += i < hi ? a.tag_cnt[i] : 0;
             }
             const long long inc = wave_incl_scan(own_sum);
             long long run = inc - own_sum;
             for (int j = 0; j < PER; ++j) {
-                const long long c = kc[lane * PER + j];
-                kc[lane * PER + j] = run;
+                const int64_t i = lo + lane * PER + j;
+                const long long c = i < hi ? a.tag_cnt[i] : 0;
+                if (!wide) kc[lane * PER + j] = (int32_t)run;
+                else if (i < hi) a.tag_cnt[i] = run;
                 run += c;
             }
+            if (wide) __threadfence();  // the offsets reach L2 before the atomics below
             __builtin_amdgcn_wave_barrier();
         }
         {
@@ -213,13 +224,39 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
                         const int L = l1 - l0;
                         if (pass == 0) {
                             M += (long long)L * sz;
-                            for (int g = head; g >= 0; g = nxt[g]) kc[g] += L;
+                            for (int g = head; g >= 0; g = nxt[g]) {
+                                const int k = kc[g];
+                                if (k > lim - L) {
+                                    // the count leaves 32 bits: move it to memory
+                                    unsigned long long *slot =
+                                        reinterpret_cast<unsigned long long *>(&a.tag_cnt[lo + g]);
+                                    const unsigned long long add = (unsigned long long)((long long)k + L);
+                                    const unsigned long long bit = 1ull << (g & 63);
+                                    if (spill[g >> 6] & bit) {
+                                        atomicAdd(slot, add);
+                                    } else {
+                                        atomicExch(slot, add);
+                                        spill[g >> 6] |= bit;
+                                    }
+                                    kc[g] = 0;
+                                } else {
+                                    kc[g] = k + L;
+                                }
+                            }
                         } else {
                             // (the first label is read once: the output
                             // stores would otherwise force a reload per tag)
                             const int32_t lab0 = L > 0 ? a.lab[l0] : 0;
                             for (int g = head; g >= 0; g = nxt[g]) {
-                                const long long k = kc[g];
+                                long long k;
+                                if (wide) {
+                                    k = (long long)atomicAdd(
+                                        reinterpret_cast<unsigned long long *>(&a.tag_cnt[lo + g]),
+                                        (unsigned long long)L);
+                                } else {
+                                    k = kc[g];
+                                    kc[g] = (int32_t)(k + L);
+                                }
                                 for (int l = 0; l < L; ++l) {
                                     const long long at = base + k + l;
                                     if (at < a.cap) {
@@ -229,7 +266,6 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
                                         o->label = l == 0 ? lab0 : a.lab[l0 + l];
                                     }
                                 }
-                                kc[g] = k + L;
                             }
                         }
                     }
@@ -244,8 +280,11 @@ __global__ __launch_bounds__(MT) void dfa_merged_kernel(MergedArgs a) {
                 for (int g = lane; g < SEG; g += 64) {
                     const int64_t i = lo + g;
                     if (i < hi) {
-                        a.tag_cnt[i] = kc[g];
-                        sum += kc[g];
+                        long long c = kc[g];
+                        if ((spill[g >> 6] >> (g & 63)) & 1)  // read back at L2
+                            c += (long long)atomicAdd(reinterpret_cast<unsigned long long *>(&a.tag_cnt[i]), 0ull);
+                        a.tag_cnt[i] = c;
+                        sum += c;
                     }
                 }
                 sum = wave_sum(sum);

@@ -231,6 +231,7 @@ struct Knobs {
     int64_t table_budget = -1; // DFA: largest LDS-resident table
     int32_t pair_cache = 1;    // NFA: two-symbol cache allowed
     int32_t merged = 0;        // DFA: tag-merged stepping
+    int32_t merged_lim = 0;    // DFA, tag-merged: 32-bit count limit (0 = 2^31 - 1)
 };
 
 // Resident workgroups of a launch: `wpc` per compute unit (at most the

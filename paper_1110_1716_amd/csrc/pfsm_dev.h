@@ -174,6 +174,7 @@ struct MergedArgs {
     long long *seg_cnt;         // [n_segs] matches of each segment
     long long *seg_base;        // [n_segs + 1] their exclusive scan
     int32_t pass;               // 0: count launch, 1: write launch
+    int32_t narrow_max;         // largest per-start count or segment offset kept in 32-bit LDS words
 };
 
 // Host-side kernel handles (defined in the .hip translation units).

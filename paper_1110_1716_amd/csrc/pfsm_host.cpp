@@ -530,6 +530,7 @@ static int merged_launch(pfsm_t *h, const uint8_t *x, int64_t n, MatchOut *out, 
     a.n_segs = (int32_t)n_segs;
     a.bstats = w->bstats;
     a.tag_cnt = w->m_tag;
+    a.narrow_max = h->knobs.merged_lim > 0 ? h->knobs.merged_lim : INT32_MAX;
     a.seg_cnt = w->m_seg;
     a.seg_base = w->m_seg + n_segs;
     const int waves = kMergedThreads / 64;
@@ -606,6 +607,10 @@ int pfsm_set_option(pfsm_t *h, int32_t option, int64_t value, void *hip_stream) 
             return fail(PFSM_ENOSYS, "tag-merged stepping needs a DFA with at most %d states", kMergedStates);
         k->merged = (int32_t)value;
         return PFSM_OK;
+    case PFSM_OPT_MERGED_COUNT_LIMIT:
+        if (value < 0 || value > INT32_MAX) return fail(PFSM_EINVAL, "merged count limit must be in [0, 2^31 - 1]");
+        k->merged_lim = (int32_t)value;
+        return PFSM_OK;
     case PFSM_OPT_PAIR_CACHE:
         if (h->kind == 0) return fail(PFSM_ENOSYS, "the pair cache applies to NFA handles");
         if (value != 0 && value != 1) return fail(PFSM_EINVAL, "pair cache must be 0 or 1");
@@ -635,6 +640,7 @@ int pfsm_get_option(const pfsm_t *h, int32_t option, int64_t *value) {
         *value = h->kind == 1 ? nfa_occupancy(h->nfa.get()) : (k->merged && h->merged_ok ? h->m_occ : h->occ);
         return PFSM_OK;
     case PFSM_OPT_MERGED_WALKS: *value = k->merged; return PFSM_OK;
+    case PFSM_OPT_MERGED_COUNT_LIMIT: *value = k->merged_lim; return PFSM_OK;
     case PFSM_OPT_RESIDENT_TABLE:
         if (h->kind == 1) return fail(PFSM_ENOSYS, "the table encoding applies to DFA handles");
         *value = (h->enc == kEnc8 || h->enc == kEnc8D || h->enc == kEnc16) ? 1 : 0;

@@ -117,3 +117,25 @@ def test_tuner_picks_merged_for_long_walks(P):
         assert np.array_equal(out.cpu().numpy(), ref)
     finally:
         h.free()
+
+
+@pytest.mark.parametrize("limit", [1, 3, 40])
+def test_count_limit_memory_paths(P, limit):
+    # a small 32-bit limit moves per-start counts to memory during the count
+    # walk and keeps whole segments' offsets there during the write walk;
+    # matches and work counters stay those of the oracle
+    cases = [(W.log_search(n=256 << 10, line_mean=512).automaton, W.log_search(n=256 << 10, line_mean=512).data),
+             (W.sigma_plus_dfa(labels=(0, 5)), np.random.default_rng(3).integers(0, 256, 3000, dtype=np.uint8))]
+    for fsm, x in cases:
+        ref, wk = oracle.scan(fsm, x)
+        h = P.pfsm_load(fsm)
+        try:
+            P.pfsm_set_option(h, P.PFSM_OPT_MERGED_WALKS, 1)
+            P.pfsm_set_option(h, P.PFSM_OPT_MERGED_COUNT_LIMIT, limit)
+            assert P.pfsm_get_option(h, P.PFSM_OPT_MERGED_COUNT_LIMIT) == limit
+            n, out = P.pfsm_scan(h, dev(x))
+            assert np.array_equal(out.cpu().numpy(), ref)
+            st = P.pfsm_last_stats(h)
+            assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
+        finally:
+            h.free()
