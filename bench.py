@@ -10,8 +10,9 @@ with events around the timed region; --eager launches them one by one with
 events around each instead.
 
 Prints one JSON line with GB/s (value), transitions/s, the single-scan
-latency distribution of the synchronous call, the roofline position of the
-scan kernel and the CPU oracle's throughput on the host cores, followed by
+latency distribution of the synchronous call, the scan kernel's position
+against the HBM roofline (and, for the per-start DFA kernel, against the LDS
+lookup rate) and the CPU oracle's throughput on the host cores, followed by
 the batched, served, long-walk, streamed and autotuned measurements (each
 can be skipped).  --workload cfg3 or log measures the NFA union or the
 tag-merged log search the same way instead (for profiling runs).
@@ -32,6 +33,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# LDS lookups: 32 lane reads (one per bank slot, a wave's 64 addresses in two
+# clocks) per clock per CU x 256 CUs x 2.4 GHz, in G lookups/s
+LDS_PEAK_GLOOKUPS = 32 * 256 * 2.4
 MATCH_BYTES = 12       # one (start, end, label) int32 triple
 ROTATE_BYTES = 1 << 30
 
@@ -572,6 +576,12 @@ def main():
                      "traffic": measured_traffic(args.workload),
                      "kernel": kernel, "kernel_avg_us": round(kern_avg_s * 1e6, 3),
                      "alg_bytes_per_launch": int(alg_bytes)},
+        "lds_roofline": ({"bound": "lds", "achieved": round(transitions / kern_avg_s / 1e9, 2),
+                          "peak": LDS_PEAK_GLOOKUPS, "unit": "Glookup/s",
+                          "frac": round(transitions / kern_avg_s / 1e9 / LDS_PEAK_GLOOKUPS, 4),
+                          "lookups_per_launch": int(transitions),
+                          "note": "one table lookup per instance-step (T)"}
+                         if kernel == "dfa_scan_kernel" else None),
         "wall_s_timed": round(wall, 4),
         "timing": timing,
         "one_stream": {"GB/s": round(n / (float(kern_ms.mean()) / 1e3) / 1e9, 2),
