@@ -183,12 +183,15 @@ def batched_vs_plain(replays: int):
                       "p99_ms": round(float(np.percentile(lat, 99)), 2)}}
 
 
-def served(n_req: int):
+def served(n_req: int, n_plain: int = 1000):
     """Served scans: 8 resident automata (4 random 16-state DFAs over abcd, 4
     NFA unions of 2,000 signatures), requests log-uniform 256 B-4 MiB.  The
     closed-loop capacity is the throughput with every request queued at once;
     then requests arrive by a Poisson process at 50 % and 90 % of it.
-    Latency = scheduled arrival -> results on the host (server timestamps)."""
+    Latency = scheduled arrival -> results on the host (server timestamps).
+    The plain path serves the first `n_plain` capacity requests one at a
+    time: copy the bytes to the device, synchronous pfsm_scan, copy the
+    matches to the host."""
     import workloads as W
     import paper_1110_1716_amd as P
     wl = W.cfg5()
@@ -205,7 +208,7 @@ def served(n_req: int):
         for i in ids:
             sv.wait(i, release=False)
             done = max(done, sv.times(i)[1])
-            sv.wait(i)
+            sv.release(i)
         return sum(len(x) for _, x in reqs) / ((done - t0) / 1e9)
 
     def open_loop(reqs, lam):
@@ -221,7 +224,7 @@ def served(n_req: int):
         for i, t in zip(ids, arr):
             sv.wait(i, release=False)
             done = sv.times(i)[1]
-            sv.wait(i)
+            sv.release(i)
             lat.append((done - t) / 1e3)
             last = max(last, done)
         lat = np.asarray(lat)
@@ -239,6 +242,20 @@ def served(n_req: int):
     res["server"] = sv.stats()
     res["admission"] = "FIFO into one of two batch slots while bytes + output estimate fit a 2 GiB budget"
     sv.close()
+
+    import torch
+    plain_reqs = cap_reqs[:n_plain]
+    for a, x in plain_reqs[:16]:
+        P.pfsm_scan(hs[a], torch.from_numpy(x).cuda())[1].cpu()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, x in plain_reqs:
+        P.pfsm_scan(hs[a], torch.from_numpy(x).cuda())[1].cpu()
+    plain_s = time.perf_counter() - t0
+    plain_gbs = sum(len(x) for _, x in plain_reqs) / plain_s / 1e9
+    res["plain"] = {"gbs": round(plain_gbs, 3), "requests": len(plain_reqs),
+                    "path": "per request: host-to-device copy, synchronous pfsm_scan, matches copied to the host"}
+    res["capacity_vs_plain"] = round(capacity / 1e9 / plain_gbs, 2)
     for h in hs:
         h.free()
     return res

@@ -335,9 +335,10 @@ int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *byte
 int pfsm_server_submit_borrowed(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n,
                                 int64_t *id);
 /* Block until request `id` is done; *matches (host memory owned by the
- * server until pfsm_server_release) holds its *n_matches matches in
- * ascending (start, end, label) order.  Errors: PFSM_ENOENT, or the error
- * the request's batch met.                                                */
+ * server until pfsm_server_release; NULL when *n_matches is 0) holds its
+ * *n_matches matches in ascending (start, end, label) order.  Errors:
+ * PFSM_ENOENT, PFSM_ENOMEM when the host result buffer could not be
+ * allocated, or the error the request's batch met.                        */
 int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches, int64_t *n_matches);
 /* When request `id` was submitted and finished (results on the host), in
  * CLOCK_MONOTONIC nanoseconds; *t_done_ns is 0 while it is not finished.

@@ -470,6 +470,10 @@ class Server:
             _check(lib.pfsm_server_release(self._ptr, int(rid)))
         return out
 
+    def release(self, rid: int) -> None:
+        """Drop a finished request (after wait(rid, release=False))."""
+        _check(load_library().pfsm_server_release(self._ptr, int(rid)))
+
     def stats(self) -> dict:
         st = _ServerStats()
         _check(load_library().pfsm_server_stats_get(self._ptr, ctypes.byref(st)))

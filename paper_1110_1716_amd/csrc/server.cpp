@@ -22,6 +22,7 @@
 #include <functional>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <tuple>
 #include <unordered_map>
@@ -52,7 +53,11 @@ struct Req {
     const uint8_t *src = nullptr;  // the request's bytes (bytes.data() or the caller's)
     int64_t n = 0;
     int64_t exact = -1;  // its match count, once a batch has counted it
-    std::vector<pfsm_match_t> result;
+    // its matches: allocated without zero-filling, since the copy from the
+    // batch output writes every row (the copy runs on the pool, so the
+    // first touch of the pages is spread over its threads)
+    std::unique_ptr<pfsm_match_t[]> result;
+    int64_t n_result = 0;
     int status = PFSM_OK;
     bool done = false;
 };
@@ -334,8 +339,14 @@ struct pfsm_server {
                 density[r->aut] = std::max(d, 0.8 * density[r->aut] + 0.2 * d);
             }
             if (whole[j]) {
-                r->result.resize(k);
-                if (k) parts.emplace_back(r->result.data(), m + mo[j], k * (int64_t)sizeof(pfsm_match_t));
+                r->result.reset(k ? new (std::nothrow) pfsm_match_t[k] : nullptr);
+                if (k && !r->result) {
+                    r->status = PFSM_ENOMEM;
+                    r->n_result = 0;
+                } else {
+                    r->n_result = k;
+                    if (k) parts.emplace_back(r->result.get(), m + mo[j], k * (int64_t)sizeof(pfsm_match_t));
+                }
                 done.push_back(r);
             } else {
                 r->exact = k;
@@ -349,7 +360,7 @@ struct pfsm_server {
             ++st.reruns;
         }
         int64_t delivered = 0;
-        for (Req *r : done) delivered += (int64_t)r->result.size();
+        for (Req *r : done) delivered += r->n_result;
         {
             std::lock_guard<std::mutex> lk(mu);
             st.matches += delivered;
@@ -494,8 +505,8 @@ int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches
     Req *r = it->second.get();
     sv->cv_done.wait(lk, [&] { return r->done; });
     if (r->status != PFSM_OK) return fail(r->status, "request %lld failed", (long long)id);
-    *matches = r->result.data();
-    *n_matches = (int64_t)r->result.size();
+    *matches = r->result.get();
+    *n_matches = r->n_result;
     return PFSM_OK;
 }
 
