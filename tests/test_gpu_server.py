@@ -130,3 +130,32 @@ def test_bad_automaton(P):
             sv.submit(3, b"abc")
         assert ei.value.code == P.PFSM_EINVAL
     hs[0].free()
+
+
+def test_wait_then_release_and_empty_results(P):
+    # results stay readable across waits until release; a request with no
+    # matches and an empty request give empty results; release twice fails
+    autos = automata()[:1]
+    hs = [P.pfsm_load(a) for a in autos]
+    rng = np.random.default_rng(11)
+    x = (rng.integers(0, 4, 50000) + ord("a")).astype(np.uint8)
+    ref, _ = oracle.scan(autos[0], x)
+    assert len(ref) > 0
+    none = np.full(4000, ord("z"), np.uint8)  # a byte outside the alphabet: no match
+    with P.Server(hs, mem_budget=64 << 20, max_batch=8) as sv:
+        ids = [sv.submit(0, y) for _ in range(3) for y in (x, none, np.zeros(0, np.uint8))]
+        for i in ids:
+            first = sv.wait(i, release=False)
+            again = sv.wait(i, release=False)
+            assert np.array_equal(first, again)
+            t_sub, t_done = sv.times(i)
+            assert t_done >= t_sub > 0
+            sv.release(i)
+            with pytest.raises(P.PfsmError) as ei:
+                sv.release(i)
+            assert ei.value.code == P.PFSM_ENOENT
+        got = [sv.wait(sv.submit(0, y)) for y in (x, none)]
+    assert np.array_equal(got[0], ref)
+    assert got[1].shape == (0, 3)
+    for h in hs:
+        h.free()
