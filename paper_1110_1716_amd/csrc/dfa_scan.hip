@@ -29,6 +29,7 @@
 // rank.  A segment whose matches do not fit the buffer, or whose parked
 // walks outgrow the spill area, is re-walked 768 starts at a time: count,
 // scan, write.
+#include "dfa_defer.h"
 #include "scan_common.h"
 #include "stream.h"
 
@@ -375,7 +376,7 @@ __device__ __forceinline__ bool spill_walks(QEnt *q, int &qcount, QEnt *area, in
 }
 
 template <int ENC, bool kId>
-__global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
+__global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a, DfaDefer d) {
     // States of the 8-bit encodings travel in the live-start list.
     constexpr bool kPack = ENC == kEnc8 || ENC == kEnc8D;
     extern __shared__ __align__(16) uint8_t lds[];
@@ -390,10 +391,10 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
     uint32_t *mkey = reinterpret_cast<uint32_t *>(lds + a.off_m);
     int32_t *mend = reinterpret_cast<int32_t *>(mkey + MC);
     int32_t *mlab = mend + MC;
-    __shared__ int mn, ovf, sp_n, seg_s, last_s, slice_s;
+    __shared__ int mn, ovf, sp_n, seg_s, last_s, slice_s, defer_s;
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
-    __shared__ long long ex_s, base_s, segsz_s;
+    __shared__ long long ex_s, base_s, segsz_s, dat_s;
     __shared__ unsigned epoch_s;
     __shared__ int nsegs_s, segbase_s;
 
@@ -602,10 +603,34 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
 
         // The segment's count, its offset by look-back, and placement.
         const long long mine_m = block_sum<NT>(seg_m, red);
-        if (tid == 0) seg_s = take_ticket(a.ctl);  // the next segment, requested early
-        if (wv == 0) {
+        if (tid == 0) {
+            seg_s = take_ticket(a.ctl);  // the next segment, requested early
+            // Deferred placement: staging rows for the buffered matches.
+            defer_s = 0;
+            if (d.stage && !ovf) {
+                const long long at = mine_m ? (long long)atomicAdd(d.cursor, (unsigned long long)mine_m) : 0;
+                if (at + mine_m <= d.stage_cap) {
+                    defer_s = 1;
+                    dat_s = at;
+                }
+            }
+        }
+        __syncthreads();
+        const bool defer = defer_s != 0;
+        if (defer) {
+            // Publish the count and go on: the offset comes later.
+            if (tid == 0) {
+                d.seg_at[sg] = dat_s;
+                d.seg_cnt[sg] = mine_m;
+                slot_store(&a.lb[sg], lb_pack(epoch, sg == 0 ? kLbIncl : kLbAgg, mine_m));
+            }
+        } else if (wv == 0) {
             const long long ex = lookback(a.lb, sg, epoch, mine_m);
             if (lane == 0) {
+                if (d.stage) {
+                    d.seg_at[sg] = -1;
+                    d.seg_cnt[sg] = mine_m;
+                }
                 ex_s = ex;
                 const long long at = out_base + ex;
                 if (sg == n_segs - 1) *a.total = at + mine_m;
@@ -663,9 +688,9 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
                 const int bk = mk >> 22;
                 int rank = base[bk];
                 for (int j = base[bk]; j < base[bk] + hist[bk]; ++j) rank += mkey[memb[j]] < mk;
-                const long long at = at0 + rank;
-                if (at < a.cap) {
-                    MatchOut *p = &a.out[at];
+                const long long at = defer ? dat_s + rank : at0 + rank;
+                if (defer || at < a.cap) {
+                    MatchOut *p = defer ? &d.stage[at] : &a.out[at];
                     p->start = (int32_t)(seg_lo + (mk >> 16));  // stream position
                     p->end = mend[e];
                     p->label = mlab[e];
@@ -702,6 +727,64 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a) {
 }
 
 __global__ void write_zero_kernel(int64_t *p) { *p = 0; }
+
+// Deferred placement in one launch, for launches of at most
+// kDeferFusedSegs segments: each workgroup sums the counts before its
+// segment, then copies the segment's staged rows (rows at or past `cap` are
+// dropped, as in the scan).  The last segment's workgroup writes the total.
+__global__ __launch_bounds__(256) void dfa_place_fused_kernel(DfaDefer d, int n_segs, int64_t *total, MatchOut *out,
+                                                              int64_t cap) {
+    __shared__ long long red[256 / 64];
+    const int sg = blockIdx.x;
+    long long v = 0;
+    for (int i = (int)threadIdx.x; i < sg; i += 256) v += d.seg_cnt[i];
+    const long long base = block_sum<256>(v, red);
+    const long long cnt = d.seg_cnt[sg];
+    if (threadIdx.x == 0) {
+        if (sg == n_segs - 1) *total = base + cnt;
+        if (sg == 0) *d.cursor = 0;
+    }
+    const long long at = d.seg_at[sg];
+    if (at < 0) return;
+    for (long long i = threadIdx.x; i < cnt; i += 256) {
+        const long long o = base + i;
+        if (o < cap) out[o] = d.stage[at + i];
+    }
+}
+
+// Deferred placement, first launch: output offsets of the segments (an
+// exclusive scan of their counts), the grand total, and the staging counter
+// cleared for the next scan on this stream.
+__global__ __launch_bounds__(1024) void dfa_place_scan_kernel(DfaDefer d, int n_segs, int64_t *total) {
+    __shared__ long long red[1024 / 64];
+    long long run = 0;
+    for (int c0 = 0; c0 < n_segs; c0 += 1024) {
+        const int i = c0 + (int)threadIdx.x;
+        const long long v = i < n_segs ? d.seg_cnt[i] : 0;
+        long long tot;
+        const long long ex = block_excl_scan<1024>(v, red, &tot);
+        if (i < n_segs) d.seg_base[i] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        *total = run;
+        *d.cursor = 0;
+    }
+}
+
+// Deferred placement, second launch: staged rows to their output positions
+// (rows at or past `cap` are dropped, as in the scan).
+__global__ __launch_bounds__(256) void dfa_place_copy_kernel(DfaDefer d, int n_segs, MatchOut *out, int64_t cap) {
+    for (int sg = blockIdx.x; sg < n_segs; sg += gridDim.x) {
+        const long long at = d.seg_at[sg];
+        if (at < 0) continue;
+        const long long cnt = d.seg_cnt[sg], base = d.seg_base[sg];
+        for (long long i = threadIdx.x; i < cnt; i += 256) {
+            const long long o = base + i;
+            if (o < cap) out[o] = d.stage[at + i];
+        }
+    }
+}
 
 template <int ENC>
 const void *pick(bool id) {
@@ -771,6 +854,20 @@ const void *dfa_kernel_fn(int enc, bool identity_map) {
     case kCold32: return pick<kCold32>(identity_map);
     default: return nullptr;
     }
+}
+
+hipError_t launch_dfa_place(const DfaDefer &d, int n_segs, int64_t *total, MatchOut *out, int64_t cap,
+                            hipStream_t s) {
+    if (n_segs <= kDeferFusedSegs) {
+        dfa_place_fused_kernel<<<n_segs, 256, 0, s>>>(d, n_segs, total, out, cap);
+        return hipGetLastError();
+    }
+    dfa_place_scan_kernel<<<1, 1024, 0, s>>>(d, n_segs, total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = n_segs < 1 ? 1 : (n_segs < 2048 ? n_segs : 2048);
+    dfa_place_copy_kernel<<<grid, 256, 0, s>>>(d, n_segs, out, cap);
+    return hipGetLastError();
 }
 
 hipError_t launch_write_zero(int64_t *p, hipStream_t stream) {

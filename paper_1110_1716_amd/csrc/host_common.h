@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <memory>
@@ -106,6 +107,11 @@ struct Workspace {
     uint32_t *big_front = nullptr;        // NFA replay frontiers
     uint32_t *big_bits = nullptr;         // NFA replay visited bits (kept clear)
     int64_t big_states = 0;
+    MatchOut *defer_rows = nullptr;       // DFA deferred placement: staged rows
+    int64_t c_defer_rows = 0;
+    long long *defer_seg = nullptr;       //   per segment: first row, count, offset
+    int64_t c_defer_seg = 0;
+    unsigned long long *defer_cursor = nullptr;
 
     ~Workspace() {
         if (slots) (void)hipFree(slots);
@@ -120,6 +126,9 @@ struct Workspace {
         if (m_seg) (void)hipFree(m_seg);
         if (big_front) (void)hipFree(big_front);
         if (big_bits) (void)hipFree(big_bits);
+        if (defer_rows) (void)hipFree(defer_rows);
+        if (defer_seg) (void)hipFree(defer_seg);
+        if (defer_cursor) (void)hipFree(defer_cursor);
     }
 };
 
@@ -188,6 +197,34 @@ inline int grow_lb(Workspace *w, int need) {
     if (w->lb) HIP_TRY(hipFree(w->lb));
     w->lb = nb;
     w->lb_cap = need;
+    return PFSM_OK;
+}
+
+// Buffers of the DFA scan's deferred placement: n_segs segments and `rows`
+// staged rows at least (grown, never shrunk; the cursor starts at zero).
+inline int grow_defer(Workspace *w, int64_t n_segs, int64_t rows) {
+    if (n_segs <= w->c_defer_seg && rows <= w->c_defer_rows && w->defer_cursor) return PFSM_OK;
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (!w->defer_cursor) {
+        HIP_TRY(hipMalloc(&w->defer_cursor, sizeof(unsigned long long)));
+        HIP_TRY(hipMemset(w->defer_cursor, 0, sizeof(unsigned long long)));
+    }
+    if (n_segs > w->c_defer_seg) {
+        const int64_t c = std::max<int64_t>(n_segs, 1024);
+        if (w->defer_seg) HIP_TRY(hipFree(w->defer_seg));
+        w->defer_seg = nullptr;
+        w->c_defer_seg = 0;
+        HIP_TRY(hipMalloc(&w->defer_seg, sizeof(long long) * 3 * (size_t)c));
+        w->c_defer_seg = c;
+    }
+    if (rows > w->c_defer_rows) {
+        if (w->defer_rows) HIP_TRY(hipFree(w->defer_rows));
+        w->defer_rows = nullptr;
+        w->c_defer_rows = 0;
+        HIP_TRY(hipMalloc(&w->defer_rows, sizeof(MatchOut) * (size_t)rows));
+        w->c_defer_rows = rows;
+    }
+    HIP_TRY(hipDeviceSynchronize());
     return PFSM_OK;
 }
 

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "dfa_defer.h"
 #include "host_common.h"
 #include "pfsm_dev.h"
 #include "pfsm_nfa.h"
@@ -485,8 +486,22 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
     a.off_m = h->off_m;
     a.off_list = h->off_list;
     a.lds_bytes = h->lds_bytes;
-    void *args[] = {&a};
+    // A plain scan places its segments' matches after the scan (dfa_defer.h).
+    DfaDefer d;
+    std::memset(&d, 0, sizeof d);
+    if (!plan && !carry && !d_base && a.n_segs > 0) {
+        const int64_t rows = std::min<int64_t>((int64_t)a.n_segs * kDfaMatchCap, kDeferRowsMax);
+        if ((rc = grow_defer(w, a.n_segs, rows))) return rc;
+        d.stage = w->defer_rows;
+        d.stage_cap = std::min<int64_t>(w->c_defer_rows, cap);
+        d.cursor = w->defer_cursor;
+        d.seg_at = w->defer_seg;
+        d.seg_cnt = w->defer_seg + w->c_defer_seg;
+        d.seg_base = w->defer_seg + 2 * w->c_defer_seg;
+    }
+    void *args[] = {&a, &d};
     HIP_TRY(hipLaunchKernel(h->kernel, dim3(grid), dim3(kDfaThreads), args, h->lds_bytes, s));
+    if (d.stage) HIP_TRY(launch_dfa_place(d, a.n_segs, d_total, out, cap, s));
     w->last_grid = grid;
     h->pool.mark(w);
     return PFSM_OK;

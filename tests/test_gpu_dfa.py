@@ -197,3 +197,58 @@ def test_dropped_walks_recounted(P):
         assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
     finally:
         h.free()
+
+
+def one_byte_dfa():
+    """Two states: q0 -> q1 (final, label 4) on bytes < 128, nothing else:
+    one match (i, i, 4) at every position holding such a byte."""
+    delta = -np.ones(2 * 256, dtype=np.int32)
+    delta[:128] = 1
+    off, lab = W.label_csr(2, {1: [4]})
+    return W.DFA(2, 256, 0, None, delta, off, lab)
+
+
+@pytest.mark.parametrize("n, seg", [(2 << 20, 256), (1 << 20, 0)])
+def test_deferred_placement_launch_paths(P, n, seg):
+    # 8,192 segments of 256 B (two follow-up launches) and the automatic
+    # segments (one fused launch): bit-exact rows and exact counts
+    wl = W.cfg2(seed=21, n=n)
+    ref, wk = oracle.scan(wl.automaton, wl.data)
+    h = P.pfsm_load(wl.automaton)
+    try:
+        P.pfsm_set_option(h, P.PFSM_OPT_SEGMENT, seg)
+        k, out = P.pfsm_scan(h, dev(wl.data))
+        assert np.array_equal(out.cpu().numpy(), ref)
+        st = P.pfsm_last_stats(h)
+        assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
+        # an output too small: the count is still exact
+        small = torch.empty((len(ref) // 3, 3), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        P.pfsm_scan_async(h, dev(wl.data), small, cnt)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == len(ref)
+        # and the next scan on the stream is whole again
+        k2, out2 = P.pfsm_scan(h, dev(wl.data))
+        assert np.array_equal(out2.cpu().numpy(), ref)
+    finally:
+        h.free()
+
+
+def test_deferred_staging_full(P):
+    # about 4.7 M matches in 9,216 segments of 1 KiB that each fit their LDS
+    # buffer: the staging rows run out part way, and the remaining segments
+    # are placed by the scan itself
+    rng = np.random.default_rng(22)
+    x = rng.integers(0, 256, 9 << 20, dtype=np.uint8)
+    fsm = one_byte_dfa()
+    ref, wk = oracle.scan(fsm, x)
+    assert len(ref) > (4 << 20) + (256 << 10)
+    h = P.pfsm_load(fsm)
+    try:
+        P.pfsm_set_option(h, P.PFSM_OPT_SEGMENT, 1024)
+        for _ in range(2):
+            k, out = P.pfsm_scan(h, dev(x), cap=len(ref))
+            assert k == len(ref)
+            assert np.array_equal(out.cpu().numpy(), ref)
+    finally:
+        h.free()
