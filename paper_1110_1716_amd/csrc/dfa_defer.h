@@ -1,16 +1,17 @@
 // Deferred placement of a plain DFA scan's matches.
 //
-// In a plain scan (one input, no carried instances, output from offset 0) a
-// segment whose matches fit its LDS buffer does not wait in the look-back
-// for its output offset.  It ranks its matches, writes them to a staging
-// area at rows it claims from a counter, publishes its count and takes its
-// next segment.  A follow-up launch on the same stream then sums the counts
-// before each segment and copies its staged rows into place (above
-// kDeferFusedSegs segments, two launches: a scan of the counts, then the
-// copy).  A segment whose matches did not fit its buffer, or that
-// finds the staging area full, is placed by the scan kernel as before; the
-// counts it sums in the look-back are the ones every segment publishes
-// before it moves on.  Batches and streams place every segment in the scan.
+// In a plain scan (one input, no carried instances, output from offset 0)
+// of at least kDeferMinSegs segments, a segment whose matches fit its LDS
+// buffer does not wait in the look-back for its output offset.  It ranks its
+// matches, writes them to a staging area at rows it claims from a counter,
+// publishes its count and takes its next segment.  A follow-up launch on the
+// same stream then sums the counts before each segment and copies its staged
+// rows into place (above kDeferFusedSegs segments, two launches: a scan of
+// the counts, then the copy).  A segment whose matches did not fit its
+// buffer, or that finds the staging area full, is placed by the scan kernel
+// as before; the counts it sums in the look-back are the ones every segment
+// publishes before it moves on.  Batches and streams place every segment in
+// the scan.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -29,6 +30,9 @@ struct DfaDefer {
 
 constexpr int64_t kDeferRowsMax = 4ll << 20;  // staging rows kept per workspace at most
 constexpr int kDeferFusedSegs = 4096;         // up to this many segments: one follow-up launch
+// Fewer segments than this are placed by the scan itself: their waits are
+// short, and a follow-up launch would add to a small scan's latency.
+constexpr int kDeferMinSegs = 64;
 
 // The follow-up launches of a deferred scan of n_segs (>= 1) segments:
 // offsets and *total, and the copy of staged rows below `cap` into `out`.

@@ -489,7 +489,7 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
     // A plain scan places its segments' matches after the scan (dfa_defer.h).
     DfaDefer d;
     std::memset(&d, 0, sizeof d);
-    if (!plan && !carry && !d_base && a.n_segs > 0) {
+    if (!plan && !carry && !d_base && a.n_segs >= kDeferMinSegs) {
         const int64_t rows = std::min<int64_t>((int64_t)a.n_segs * kDfaMatchCap, kDeferRowsMax);
         if ((rc = grow_defer(w, a.n_segs, rows))) return rc;
         d.stage = w->defer_rows;
