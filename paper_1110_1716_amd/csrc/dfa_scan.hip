@@ -23,12 +23,15 @@
 //      under the key (start - segment start, k), k = the instance's match
 //      count so far, which orders (end, label) within a start (Section III.B
 //      reporting rule).
-// At the end of a segment the workgroup finds its output offset by
-// decoupled look-back over earlier tickets (a predecessor holds an earlier
-// ticket, so it is already running) and writes every buffered match at its
-// rank.  A segment whose matches do not fit the buffer, or whose parked
-// walks outgrow the spill area, is re-walked 768 starts at a time: count,
-// scan, write.
+// At the end of a segment the workgroup publishes its match count.  In a
+// plain scan of enough segments it then writes its buffered matches, at
+// their ranks, to staging rows and moves on; a follow-up launch places them
+// (dfa_defer.h).  Otherwise it finds its output offset by decoupled
+// look-back over earlier tickets (a predecessor holds an earlier ticket, so
+// it is already running) and writes every buffered match at its rank.  A
+// segment whose matches do not fit the buffer, or whose parked walks
+// outgrow the spill area, is re-walked 768 starts at a time: count, scan,
+// write.
 #include "dfa_defer.h"
 #include "scan_common.h"
 #include "stream.h"
@@ -601,7 +604,8 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a, DfaDefer d) {
             c.M = m_before + seg_m;
         }
 
-        // The segment's count, its offset by look-back, and placement.
+        // The segment's count, then its placement: staged for a follow-up
+        // launch, or at the offset found by look-back.
         const long long mine_m = block_sum<NT>(seg_m, red);
         if (tid == 0) {
             seg_s = take_ticket(a.ctl);  // the next segment, requested early
