@@ -221,12 +221,15 @@ def test_deferred_placement_launch_paths(P, n, seg):
         assert np.array_equal(out.cpu().numpy(), ref)
         st = P.pfsm_last_stats(h)
         assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
-        # an output too small: the count is still exact
-        small = torch.empty((len(ref) // 3, 3), dtype=torch.int32, device="cuda")
+        # an output too small: the count is still exact, and the output
+        # holds the first cap matches
+        cap = len(ref) // 3
+        small = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
         P.pfsm_scan_async(h, dev(wl.data), small, cnt)
         torch.cuda.synchronize()
         assert int(cnt.item()) == len(ref)
+        assert np.array_equal(small.cpu().numpy(), ref[:cap])
         # and the next scan on the stream is whole again
         k2, out2 = P.pfsm_scan(h, dev(wl.data))
         assert np.array_equal(out2.cpu().numpy(), ref)
