@@ -7,8 +7,9 @@
 // estimate) into a free slot and enqueues the whole batch on that slot's
 // stream (planning, one scan launch per automaton, offsets, gather; see
 // batch.hip), then goes on admitting into the other slot while the first
-// batch runs.  When a slot's batch is done its matches are copied back and
-// handed to the waiting callers.  A batch whose output outgrows the
+// batch runs.  When a slot's batch is done its matches are copied back, the
+// slot takes its next batch, and only then are the matches handed to the
+// waiting callers.  A batch whose output outgrows the
 // estimate is run again at the exact size (the total is known by then).
 #include <hip/hip_runtime.h>
 #include <time.h>
@@ -353,21 +354,41 @@ struct pfsm_server {
                 redo.push_back(r);
             }
         }
-        copy_all(parts);
         if (!redo.empty()) {
             std::lock_guard<std::mutex> lk(mu);
             for (auto it = redo.rbegin(); it != redo.rend(); ++it) queue.push_front(*it);
             ++st.reruns;
         }
+        // Hand the slot to the next batch before copying these results out:
+        // its inputs and device buffers are free now, and the matches stay
+        // in h_out, which a batch touches only when it completes.
+        const int64_t t1 = now_ns();
+        const int64_t bytes = sl.bytes;
+        inflight -= charge(bytes, sl.out_cap);
+        sl.reqs.clear();
+        sl.busy = false;
+        if (admit(sl)) {
+            sl.busy = true;
+            const int lrc = launch(sl);
+            if (lrc) finish(sl, lrc);
+        }
+        const int64_t t2 = now_ns();
+        copy_all(parts);
         int64_t delivered = 0;
         for (Req *r : done) delivered += r->n_result;
         {
             std::lock_guard<std::mutex> lk(mu);
+            const int64_t t = now_ns();
+            for (Req *r : done) {
+                r->t_done = t;
+                r->done = true;
+            }
+            st.requests += (int64_t)done.size();
+            st.bytes += bytes;
             st.matches += delivered;
-            st.deliver_ns += now_ns() - t0;
+            st.deliver_ns += (t1 - t0) + (t - t2);
         }
-        sl.reqs.swap(done);
-        finish(sl, PFSM_OK);
+        cv_done.notify_all();
         return PFSM_OK;
     }
 
