@@ -1,8 +1,8 @@
 """Seeded parity sweep: random DFAs and NFAs of every table encoding, input
 lengths that cross slice, window and segment boundaries, unaligned inputs,
-and the launch settings a handle accepts.  Each case must reproduce the
-oracle's match list bit for bit and its work counters (instance-steps, live
-steps, matches)."""
+and the launch settings a handle accepts; and DFA scans of 256 KiB-4 MiB
+with automatic segments.  Each case must reproduce the oracle's match list
+bit for bit and its work counters (instance-steps, live steps, matches)."""
 import numpy as np
 import pytest
 
@@ -150,3 +150,39 @@ def test_sweep_stream(P, seed):
     finally:
         h.free()
     assert total == len(ref)
+
+
+def make_large_case(seed):
+    """DFA scans of 256 KiB-4 MiB with automatic segments: enough segments
+    for plain scans to stage their matches and place them afterwards."""
+    rng = np.random.default_rng(50000 + seed)
+    kind = seed % 3
+    n = int(rng.choice([256 << 10, 300001, 1 << 20, 2 << 20, 4 << 20]))
+    if kind == 0:
+        ns = int(rng.choice([16, 64, 256, 1000]))
+        fsm = W.random_table_dfa(rng, ns, 256, float(rng.uniform(0.85, 0.97)),
+                                 int(rng.integers(1, min(17, ns // 4 + 1))))
+        x = rng.integers(0, 256, n, dtype=np.uint8)
+    elif kind == 1:
+        fsm = W.random_dfa(rng, int(rng.integers(2, 60)), 4, p_dead=float(rng.uniform(0.45, 0.8)),
+                           n_finals=int(rng.integers(1, 4)), max_labels=3, n_labels=5)
+        x = (rng.integers(0, 4, n) + ord("a")).astype(np.uint8)
+        x[rng.random(n) < 0.02] = ord("e")
+    else:
+        wl = W.cfg2(seed=int(rng.integers(0, 1 << 30)), n=n)
+        fsm, x = wl.automaton, wl.data
+    return fsm, x
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_sweep_large(P, seed):
+    fsm, x = make_large_case(seed)
+    ref, wk = oracle.scan(fsm, x)
+    h = P.pfsm_load(fsm)
+    try:
+        n, out = P.pfsm_scan(h, torch.from_numpy(x).cuda())
+        assert np.array_equal(out.cpu().numpy(), ref)
+        st = P.pfsm_last_stats(h)
+        assert (st["transitions"], st["activations"], st["matches"]) == (wk["T"], wk["X"], len(ref))
+    finally:
+        h.free()
