@@ -325,7 +325,8 @@ def cfg2(seed: int = 2, n: int = 16 * MiB, plant_every: int = 4 * KiB) -> Worklo
         off = blk * plant_every + int(rng.integers(0, plant_every - w.size + 1))
         x[off:off + w.size] = w
         plants.append((off, w.size))
-    return Workload("random DFA 256 states x 256 symbols, 16 MiB uniform bytes + planted walks",
+    size = f"{n >> 20} MiB" if n % MiB == 0 else f"{n} B"
+    return Workload(f"random DFA 256 states x 256 symbols, {size} uniform bytes + planted walks",
                     d, x, seed, {"plants": plants})
 
 
