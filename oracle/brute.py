@@ -8,6 +8,9 @@ states reachable through symbol edges with epsilon edges interleaved) and
 every label of every final state it ends in is reported as (s, e, label)
 (Section III.B reporting rule).  No pruning, no caching, nothing shared
 between substrings: O(n^3) set steps.
+
+``work`` counts the scan's work counters (instance-steps T and state
+activations X) from their definition, one start at a time.
 """
 from __future__ import annotations
 
@@ -72,3 +75,75 @@ def matches(fsm, x: bytes) -> List[Tuple[int, int, int]]:
             for lab in run(fsm, x[s:e + 1]):
                 out.append((s, e, lab))
     return sorted(out)
+
+
+def _coreachable(fsm) -> Set[int]:
+    """States from which a final state (non-empty label set) can be reached
+    through edges that some byte, or epsilon, can take (reverse search)."""
+    n = fsm.n_states
+    preds: List[List[int]] = [[] for _ in range(n)]
+    if fsm.kind == "dfa":
+        used = set(range(fsm.n_symbols)) if fsm.byte_to_symbol is None else \
+            {int(v) for v in fsm.byte_to_symbol if int(v) >= 0}
+        for q in range(n):
+            for s in used:
+                t = int(fsm.delta[q * fsm.n_symbols + s])
+                if t >= 0:
+                    preds[t].append(q)
+    else:
+        for q in range(n):
+            for e in range(int(fsm.row_ptr[q]), int(fsm.row_ptr[q + 1])):
+                k = int(fsm.edge_class[e])
+                if k == -1 or any(int(w) for w in fsm.class_bits[k * 8:k * 8 + 8]):
+                    preds[int(fsm.edge_dst[e])].append(q)
+    good = {q for q in range(n) if fsm.labels_of(q)}
+    todo = list(good)
+    while todo:
+        q = todo.pop()
+        for p in preds[q]:
+            if p not in good:
+                good.add(p)
+                todo.append(p)
+    return good
+
+
+def work(fsm, x: bytes) -> Tuple[int, int]:
+    """The work counters of the scan, from their definition, per start.
+
+    For every start s the instance's state set is advanced one byte at a time
+    (epsilon-closed after each byte) and restricted to states that can still
+    reach a final state.  T counts the bytes consumed while the set was
+    non-empty before the byte (the byte that empties it included); X adds
+    the size of the set after each such byte."""
+    x = bytes(x)
+    good = _coreachable(fsm)
+    T = X = 0
+    for s in range(len(x)):
+        if fsm.kind == "dfa":
+            cur: Set[int] = {fsm.q0}
+        else:
+            cur = _eps_closure(fsm, {fsm.q0})
+        for e in range(s, len(x)):
+            b = x[e]
+            nxt: Set[int] = set()
+            if fsm.kind == "dfa":
+                sym = b if fsm.byte_to_symbol is None else int(fsm.byte_to_symbol[b])
+                if sym >= 0:
+                    for q in cur:
+                        t = int(fsm.delta[q * fsm.n_symbols + sym])
+                        if t >= 0:
+                            nxt.add(t)
+            else:
+                for q in cur:
+                    for k in range(int(fsm.row_ptr[q]), int(fsm.row_ptr[q + 1])):
+                        c = int(fsm.edge_class[k])
+                        if c >= 0 and _in_class(fsm, c, b):
+                            nxt.add(int(fsm.edge_dst[k]))
+                nxt = _eps_closure(fsm, nxt)
+            nxt &= good
+            T += 1
+            X += len(nxt)
+            if not nxt:
+                break
+            cur = nxt
+    return T, X

@@ -348,3 +348,115 @@ def test_generated_nfas_vs_brute_force(fsm, x):
     for prune in (True, False):
         for memo in (True, False):
             assert as_list(oracle.scan(fsm, x, prune=prune, memo=memo, threads=2)[0]) == ref
+
+
+# ---------------------------------------------------------------- work counters of NFAs
+#
+# T (instance-steps) and X (state activations) are the numerators of the
+# reported rates and the GPU's counters are compared with them, so they are
+# pinned here by closed forms and by a per-start set simulation.
+
+ANY = list(range(256))
+
+
+def sigma_plus_union_nfa(k):
+    """k copies of Sigma+ under an ancillary initial state (Section III.A):
+    q0 -eps-> c_j -any-> f_j -any-> f_j, f_j final with label j."""
+    src, cls, dst, finals = [], [], [], {}
+    for j in range(k):
+        c, f = 1 + 2 * j, 2 + 2 * j
+        src += [0, c, f]
+        cls += [-1, 0, 0]
+        dst += [c, f, f]
+        finals[f] = [j]
+    return W.build_nfa(1 + 2 * k, 0, src, cls, dst, [ANY], finals)
+
+
+def literal_chain_nfa(length):
+    """q0 -a-> 1 -a-> ... -a-> length (final)."""
+    src = list(range(length))
+    return W.build_nfa(length + 1, 0, src, [0] * length, [s + 1 for s in src], [[ord("a")]], {length: [0]})
+
+
+def eps_fanout_nfa(k):
+    """q0 -eps-> c_j; c_j -a-> d_j -eps-> e_j -eps-> g_j (g_j final, label j);
+    c_j -a-> z_j, from which no final state is reachable."""
+    src, cls, dst, finals = [], [], [], {}
+    for j in range(k):
+        c, d, e, g, z = (1 + 5 * j + i for i in range(5))
+        src += [0, c, d, e, c, z]
+        cls += [-1, 0, -1, -1, 0, 0]
+        dst += [c, d, e, g, z, z]
+        finals[g] = [j]
+    return W.build_nfa(1 + 5 * k, 0, src, cls, dst, [[ord("a")]], finals)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5])
+@pytest.mark.parametrize("n", [1, 2, 9, 40])
+def test_nfa_work_sigma_plus_union(k, n):
+    """Every instance lives to the end of the input holding k states: T =
+    n(n+1)/2 and X = k n(n+1)/2 (one activation per state per step)."""
+    x = np.random.default_rng(n).integers(0, 256, n, dtype=np.uint8)
+    for memo in (True, False):
+        got, wk = oracle.scan(sigma_plus_union_nfa(k), x, memo=memo, threads=2)
+        assert len(got) == k * n * (n + 1) // 2
+        assert wk["T"] == n * (n + 1) // 2
+        assert wk["X"] == k * n * (n + 1) // 2
+
+
+@pytest.mark.parametrize("length", [1, 3, 6])
+@pytest.mark.parametrize("n", [1, 4, 7, 20])
+def test_nfa_work_literal_chain(length, n):
+    """a^length on a^n: a start lives min(length, n - s) bytes in one state,
+    and the byte after the final state ends it, when there is one."""
+    for memo in (True, False):
+        got, wk = oracle.scan(literal_chain_nfa(length), b"a" * n, memo=memo, threads=2)
+        assert as_list(got) == [(s, s + length - 1, 0) for s in range(n - length + 1)]
+        assert wk["T"] == sum(min(length + 1, n - s) for s in range(n))
+        assert wk["X"] == sum(min(length, n - s) for s in range(n))
+
+
+@pytest.mark.parametrize("k", [1, 3])
+@pytest.mark.parametrize("n", [1, 2, 10])
+def test_nfa_work_epsilon_fan_out(k, n):
+    """After one 'a' an instance holds d_j, e_j, g_j for every j (closure
+    applied at once; z_j dropped, it reaches no final state): X = 3k per
+    start, and the second byte ends it: T = min(2, n - s) per start."""
+    for memo in (True, False):
+        got, wk = oracle.scan(eps_fanout_nfa(k), b"a" * n, memo=memo, threads=2)
+        assert as_list(got) == [(s, s, j) for s in range(n) for j in range(k)]
+        assert wk["X"] == 3 * k * n
+        assert wk["T"] == sum(min(2, n - s) for s in range(n))
+
+
+def test_nfa_work_without_pruning_keeps_dead_branch():
+    """With pruning off, z_j stays in the set: it is activated once per byte
+    the instance reads (first 'a', then every later 'a' on its self loop)."""
+    n, k = 6, 2
+    _, wk = oracle.scan(eps_fanout_nfa(k), b"a" * n, prune=False, threads=1)
+    # per start: 4k states after the first byte (d, e, g, z), then k (z) per byte
+    assert wk["X"] == sum(4 * k + k * (n - s - 1) for s in range(n))
+    assert wk["T"] == n * (n + 1) // 2
+
+
+@settings(max_examples=120, deadline=None)
+@given(small_nfas(), st.binary(max_size=12).map(lambda b: bytes(ord("a") + c % 4 for c in b)))
+def test_generated_nfa_work_vs_per_start_sets(fsm, x):
+    T, X = brute.work(fsm, x)
+    for memo in (True, False):
+        _, wk = oracle.scan(fsm, x, memo=memo, threads=2)
+        assert (wk["T"], wk["X"]) == (T, X)
+
+
+@settings(max_examples=120, deadline=None)
+@given(small_dfas(), st.binary(max_size=12).map(lambda b: bytes(ord("a") + c % 4 for c in b)))
+def test_generated_dfa_work_vs_per_start_sets(fsm, x):
+    assert tuple(oracle.scan(fsm, x, threads=2)[1].values()) == brute.work(fsm, x)
+
+
+def test_cfg_sample_work_vs_per_start_sets():
+    """The NFA union recipe on a short sample: counters equal the per-start
+    simulation (chains, byte classes, the any-byte gap states)."""
+    wl = W.cfg3(n=600, n_patterns=40, plant_rate=2e-2)
+    _, wk = oracle.scan(wl.automaton, wl.data)
+    assert (wk["T"], wk["X"]) == brute.work(wl.automaton, bytes(wl.data))
