@@ -264,7 +264,7 @@ int pfsm_tune(pfsm_t *h, const uint8_t *d_sample, int64_t n, int32_t reps, pfsm_
               void *hip_stream);
 
 /* ---------------------------------------------------------------------
- * Streaming scans: chained data partitioning (Section III.D.3).  A stream's
+ * Streaming scans: chained data partitioning (Section III.D.2).  A stream's
  * bytes are fed in pieces; every instance still live when a piece ends is
  * carried into the next one as its start and state set, so the matches of
  * all pieces together are exactly those of one pfsm_scan of the

@@ -58,7 +58,7 @@ struct MatchOut {
 };
 
 // Instances still live when a scan reaches the end of its input (chained
-// partitioning, Section III.D.3): each appends one (start, state) pair per
+// partitioning, Section III.D.2): each appends one (start, state) pair per
 // state it holds, start as a position of the whole stream (the piece's
 // first byte is `base`).  Pairs arrive in no particular order and may repeat;
 // *n counts every pair asked for, including those past cap.  Off when pairs

@@ -1,4 +1,4 @@
-// Streaming scans (chained partitioning, Section III.D.3): argument blocks
+// Streaming scans (chained partitioning, Section III.D.2): argument blocks
 // of the kernels that carry live instances from one piece of a stream to the
 // next (internal to libpfsm).
 #pragma once

@@ -1,6 +1,6 @@
 // Streaming scans: a stream's bytes arrive in pieces, and the matches of the
 // pieces together are those of one scan of the whole stream.  This is the
-// chained form of data partitioning (Section III.D.3): an instance still
+// chained form of data partitioning (Section III.D.2): an instance still
 // live when a piece ends is handed to the next piece as (start, state set)
 // and continues there, so no piece re-reads earlier bytes.
 //

@@ -1,4 +1,4 @@
-"""Streaming scans (chained data partitioning, Section III.D.3) against the
+"""Streaming scans (chained data partitioning, Section III.D.2) against the
 oracle: a stream fed in pieces must report, piece by piece, exactly the
 oracle's whole-stream matches whose end lies in that piece, in (start, end,
 label) order."""
