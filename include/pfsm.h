@@ -168,7 +168,9 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
 int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
                     int64_t cap, int64_t *d_n_matches, void *hip_stream);
 
-/* Scan many byte streams, each against one of several handles, in one pass.
+/* Scan many byte streams, each against one of several handles, in one pass:
+ * the union model of Section III.A applied per stream (each stream's
+ * matches are those of pfsm_scan of its bytes alone against its handle).
  *   hs                  host array of n_automata handles.
  *   d_data              device bytes of all streams, concatenated.
  *   d_stream_off        device int64 [n_streams + 1]: stream i is
@@ -191,7 +193,8 @@ int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data
                     int32_t n_streams, pfsm_match_t *d_out, int64_t cap, int64_t *d_match_off,
                     int64_t *n_matches, void *hip_stream);
 
-/* pfsm_scan_batch without any host round trip: every step (planning, one
+/* pfsm_scan_batch (Section III.A per stream) without any host round trip:
+ * every step (planning, one
  * scan launch per automaton, offsets, gather) is enqueued on `hip_stream`
  * and nothing is allocated, so the call can be captured into a HIP graph
  * and replayed.  The grand total is d_match_off[n_streams]; the caller
@@ -352,9 +355,12 @@ int pfsm_server_stats_get(pfsm_server_t *sv, pfsm_server_stats *out);
 /* Finish every queued request, stop the worker and free the server.       */
 void pfsm_server_destroy(pfsm_server_t *sv);
 
-/* Work counters of the most recent completed scan of `h` on `hip_stream`.
- * Synchronises the stream.  Errors: PFSM_EINVAL, PFSM_ENOENT (no scan yet),
- * PFSM_EHIP.                                                              */
+/* Work counters of the most recent completed scan of `h` on `hip_stream`
+ * (the step counts Section III.C bounds).  Counters are kept per stream,
+ * because one handle may scan on several streams at once; the call takes the
+ * stream and synchronises it.  No elapsed time is kept: timing every scan
+ * would add events to every launch, so callers time with their own events.
+ * Errors: PFSM_EINVAL, PFSM_ENOENT (no scan yet), PFSM_EHIP.              */
 int pfsm_last_stats(pfsm_t *h, pfsm_stats *out, void *hip_stream);
 
 /* Release a handle and every device buffer it owns.  Waits for the device
