@@ -367,6 +367,14 @@ int pfsm_last_stats(pfsm_t *h, pfsm_stats *out, void *hip_stream);
  * work that uses them.  NULL is ignored.                                   */
 void pfsm_free(pfsm_t *h);
 
+/* Release the buffers the library keeps across calls for batched scans
+ * (per device and stream: planning arrays, the match stage, a pinned
+ * read-back word).  Waits for the device first.  Call it at teardown, after
+ * every batch has finished and before the HIP runtime shuts down; a later
+ * batch allocates them again.  Handles, streams and servers are released by
+ * their own calls.                                                         */
+void pfsm_release_cached(void);
+
 /* Static description of an error code. */
 const char *pfsm_strerror(int code);
 

@@ -15,8 +15,10 @@ Names follow the C ABI: ``pfsm_load_dfa``, ``pfsm_load_nfa``,
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Tuple
 
 import numpy as np
@@ -49,7 +51,7 @@ EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pa
            "pfsm_server_wait",
            "pfsm_server_times", "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy",
            "pfsm_stream_open", "pfsm_stream_feed", "pfsm_stream_info", "pfsm_stream_close",
-           "pfsm_set_option", "pfsm_get_option", "pfsm_tune")
+           "pfsm_set_option", "pfsm_get_option", "pfsm_tune", "pfsm_release_cached")
 
 
 class PfsmError(RuntimeError):
@@ -114,6 +116,7 @@ def load_library(path: str = LIB_PATH):
         "pfsm_scan_batch_async": (ctypes.c_int, [vp, i32, vp, vp, vp, i32, vp, i64, vp, vp]),
         "pfsm_last_stats": (ctypes.c_int, [vp, ctypes.POINTER(_Stats), vp]),
         "pfsm_free": (None, [vp]),
+        "pfsm_release_cached": (None, []),
         "pfsm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "pfsm_server_create": (ctypes.c_int, [ctypes.POINTER(vp), vp, i32, i64, i32]),
         "pfsm_server_submit": (ctypes.c_int, [vp, i32, vp, i64, ctypes.POINTER(i64)]),
@@ -137,7 +140,28 @@ def load_library(path: str = LIB_PATH):
         f.restype = res
         f.argtypes = args
     _lib = lib
+    atexit.register(_release_at_exit)
     return lib
+
+
+# Objects still open when the interpreter exits are released by an atexit
+# hook, in dependency order (servers, then streams, then handles, then the
+# library's cached batch buffers), while the HIP runtime is still up: never
+# from finalizers that run in no set order during shutdown.
+_live_servers: "weakref.WeakSet" = weakref.WeakSet()
+_live_streams: "weakref.WeakSet" = weakref.WeakSet()
+_live_handles: "weakref.WeakSet" = weakref.WeakSet()
+
+
+def _release_at_exit():
+    for group in (_live_servers, _live_streams, _live_handles):
+        for obj in list(group):
+            try:
+                obj.close() if hasattr(obj, "close") else obj.free()
+            except Exception:
+                pass
+    if _lib is not None:
+        _lib.pfsm_release_cached()
 
 
 def _check(rc: int):
@@ -180,6 +204,7 @@ class Pfsm:
     def __init__(self, ptr: int, kind: str):
         self._ptr = ptr
         self.kind = kind
+        _live_handles.add(self)
 
     @property
     def ptr(self) -> int:
@@ -383,6 +408,7 @@ class Stream:
         _check(load_library().pfsm_stream_open(ctypes.byref(p), h.ptr))
         self._h = h
         self._ptr = p.value
+        _live_streams.add(self)
 
     def feed(self, x, out=None, stream=None, cap: Optional[int] = None) -> Tuple[int, "torch.Tensor"]:
         """Feed device bytes ``x``; returns (n_matches, out[:n_matches]).
@@ -442,6 +468,7 @@ class Server:
         p = ctypes.c_void_p()
         _check(lib.pfsm_server_create(ctypes.byref(p), arr, len(self._handles), int(mem_budget), int(max_batch)))
         self._ptr = p.value
+        _live_servers.add(self)
 
     def submit(self, automaton: int, data, borrow: bool = False) -> int:
         """Queue a request.  With borrow=True the server reads ``data`` (a

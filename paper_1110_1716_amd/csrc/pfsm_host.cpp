@@ -669,13 +669,22 @@ int pfsm_get_option(const pfsm_t *h, int32_t option, int64_t *value) {
 
 namespace {
 
-// Device buffers of batched scans on one stream (kept for the process).
+// Device buffers of batched scans on one stream, kept until
+// pfsm_release_cached.  The destructor makes no HIP call: it may run from
+// static destruction at exit, after the runtime has gone.
 struct BatchWs {
     int32_t *seg_first = nullptr, *seg_stream = nullptr, *n_segs = nullptr, *seg_base = nullptr;
     int64_t *bases = nullptr, *seg = nullptr, *stream_lo = nullptr, *stream_hi = nullptr;
     MatchOut *stage = nullptr;
     BatchInfo *info = nullptr, *h_info = nullptr;  // h_info: pinned
     int64_t c_first = 0, c_seg = 0, c_nsegs = 0, c_base = 0, c_bases = 0, c_lo = 0, c_hi = 0, c_stage = 0, c_segsz = 0;
+    // Frees every buffer (the device must be idle).
+    void release() {
+        void *dev[] = {seg_first, seg_stream, n_segs, seg_base, bases, seg, stream_lo, stream_hi, stage, info};
+        for (void *p : dev)
+            if (p) (void)hipFree(p);
+        if (h_info) (void)hipHostFree(h_info);
+    }
 };
 
 std::mutex g_batch_mu;
@@ -941,6 +950,14 @@ void pfsm_free(pfsm_t *h) {
     if (!h) return;
     (void)hipDeviceSynchronize();
     delete h;
+}
+
+void pfsm_release_cached(void) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (g_batch.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : g_batch) kv.second->release();
+    g_batch.clear();
 }
 
 }  // extern "C"
