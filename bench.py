@@ -51,9 +51,11 @@ def parse():
     ap.add_argument("--latency-iters", type=int, default=10000)
     ap.add_argument("--eager", action="store_true",
                     help="time one launch per scan with events around each, instead of HIP-graph replays")
-    ap.add_argument("--streams", type=int, default=4,
-                    help="the graph-replayed scans of `value` alternate over this many streams, so that "
-                         "independent scans overlap (the roofline's per-launch time comes from one stream)")
+    ap.add_argument("--overlap-streams", type=int, default=4,
+                    help="also time the scans alternating over this many streams (reported as `overlapped`; "
+                         "`value` is always one stream); 1 = skip")
+    ap.add_argument("--no-cfg3", action="store_true", help="skip the NFA-union (cfg3) measurement")
+    ap.add_argument("--cfg3-steps", type=int, default=48)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -421,6 +423,128 @@ def cpu_baseline(wl, seconds: float):
             "cpu_model": _cpu_model()}
 
 
+def time_scans(P, h, xs, out, steps: int, nstreams: int, n_ref: int, ref_rows):
+    """K back-to-back scans replayed from HIP graphs: one graph of a scan per
+    resident input copy, replayed K // copies times, and one of the remaining
+    K % copies scans; events around the whole region on the replaying
+    stream.  With nstreams > 1 the scans alternate over that many streams
+    (forked and joined inside the graph), so that independent scans overlap.
+    Every replayed count and each stream's last match list are checked
+    against the eager scan.  Returns (total ms, wall s)."""
+    import torch
+    dev = out.device
+    n_copies = len(xs)
+    ns = max(1, nstreams)
+    gss = [torch.cuda.Stream() for _ in range(ns)]
+    outs = [out] + [torch.empty_like(out) for _ in range(ns - 1)]
+    gs = gss[0]
+    warm = torch.zeros(2, dtype=torch.int64, device=dev)
+    for qi, q in enumerate(gss):
+        q.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(q):
+            for i in range(2):
+                P.pfsm_scan_async(h, xs[i % n_copies], outs[qi], warm[i:i + 1], stream=q)
+        q.synchronize()
+    cnt_g = torch.zeros(n_copies, dtype=torch.int64, device=dev)
+    reps, rest = divmod(steps, n_copies)
+    graphs = []
+    for m in ([n_copies] if reps else []) + ([rest] if rest else []):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=gs):
+            for q in gss[1:]:
+                q.wait_stream(gs)  # fork
+            for k in range(m):
+                P.pfsm_scan_async(h, xs[k], outs[k % ns], cnt_g[k:k + 1], stream=gss[k % ns])
+            for q in gss[1:]:
+                gs.wait_stream(q)  # join
+        graphs.append((g, m))
+    with torch.cuda.stream(gs):
+        for g, _ in graphs:
+            g.replay()  # untimed
+    gs.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    with torch.cuda.stream(gs):
+        t0.record(gs)
+        for _ in range(reps):
+            graphs[0][0].replay()
+        if rest:
+            graphs[-1][0].replay()
+        t1.record(gs)
+    gs.synchronize()
+    wall = time.perf_counter() - wall0
+    got = cnt_g[:min(steps, n_copies)].cpu().numpy()
+    if not np.all(got == n_ref):
+        raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
+    for o in outs[:min(ns, steps)]:
+        if not np.array_equal(o[:n_ref].cpu().numpy(), ref_rows):
+            raise SystemExit("a graph-replayed scan's matches differ from the eager scan's")
+    return t0.elapsed_time(t1), wall
+
+
+def nfa_cfg3(steps: int, cpu_seconds: float, no_cpu: bool):
+    """The 2,000-signature NFA union on 64 MiB of Zipf bytes: one-stream
+    graph-replayed scans (inputs rotated over 1 GiB of copies), the kernel's
+    work counters, the HBM and LDS-lookup rooflines of nfa_scan_kernel, and
+    the oracle timed on the host cores over whole passes (whose work counters
+    the kernel's must equal)."""
+    import torch
+    import workloads as W
+    import paper_1110_1716_amd as P
+    wl = W.cfg3()
+    n = wl.data.size
+    h = P.pfsm_load(wl.automaton)
+    try:
+        dev = torch.device("cuda:0")
+        host = torch.from_numpy(wl.data.copy())
+        xs = [host.to(dev) for _ in range(max(1, ROTATE_BYTES // n))]
+        out = torch.empty((n // 64 + 4096, 3), dtype=torch.int32, device=dev)
+        n_ref, rows = P.pfsm_scan(h, xs[0], out=out)
+        rows = rows.cpu().numpy().copy()
+        st = P.pfsm_last_stats(h)
+        total_ms, wall = time_scans(P, h, xs, out, steps, 1, n_ref, rows)
+        us = total_ms / steps * 1e3
+        alg_bytes = n + MATCH_BYTES * n_ref
+        res = {"workload": wl.name, "n_bytes": n, "seed": wl.seed, "n_states": int(wl.automaton.n_states),
+               "matches_per_scan": int(n_ref), "steps": steps, "us_per_scan": round(us, 3),
+               "GB/s": round(n / us / 1e3, 3),
+               "transitions_per_scan": int(st["transitions"]), "activations_per_scan": int(st["activations"]),
+               "transitions_per_s": round(st["transitions"] / us * 1e6, 1),
+               "activations_per_s": round(st["activations"] / us * 1e6, 1),
+               "roofline": {"bound": "hbm", "achieved": round(alg_bytes / us / 1e3, 2), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(alg_bytes / us / 1e3 / HBM_PEAK_GBS, 5),
+                            "traffic": measured_traffic("cfg3"), "kernel": "nfa_scan_kernel",
+                            "kernel_avg_us": round(us, 3), "alg_bytes_per_launch": int(alg_bytes)},
+               "lds_roofline": {"bound": "lds", "achieved": round(st["activations"] / us / 1e3, 2),
+                                "peak": LDS_PEAK_GLOOKUPS, "unit": "Glookup/s",
+                                "frac": round(st["activations"] / us / 1e3 / LDS_PEAK_GLOOKUPS, 5),
+                                "lookups_per_launch": int(st["activations"]),
+                                "note": "one state-record lookup per state activation (X)"},
+               "wall_s_timed": round(wall, 4)}
+        del xs
+    finally:
+        h.free()
+    if not no_cpu:
+        import oracle
+        threads = oracle.default_threads()
+        reps, t0, wk = 0, time.perf_counter(), None
+        while True:
+            ref, wk = oracle.scan(wl.automaton, wl.data, threads=threads)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= cpu_seconds:
+                break
+        if len(ref) != n_ref or wk["T"] != res["transitions_per_scan"] or wk["X"] != res["activations_per_scan"]:
+            raise SystemExit(f"cfg3: GPU {n_ref} matches / {res['transitions_per_scan']} T / "
+                             f"{res['activations_per_scan']} X, oracle {len(ref)} / {wk['T']} / {wk['X']}")
+        res["cpu_baseline"] = {"value": round(reps * n / el / 1e9, 5), "unit": "GB/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{reps} full passes over the 64 MiB input ({reps * n} bytes, {el:.1f} s wall); "
+                                         "its matches, T and X equal the GPU scan's",
+                               "activations_per_s": round(wk["X"] * reps / el, 1), "cpu_model": _cpu_model()}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -469,10 +593,11 @@ def main():
         P.pfsm_scan_async(h, xs[i % n_copies], out, counts[i:i + 1])
     torch.cuda.synchronize()
 
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+    overlapped = None
     if args.eager:
         # one launch per scan, events around each
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
         torch.cuda.synchronize()
@@ -489,70 +614,22 @@ def main():
         total_ms = t_start.elapsed_time(t_end)
         kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
         got = counts.cpu().numpy()
+        if not np.all(got == n_ref):
+            raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
         timing = "one launch per scan; events around each launch"
     else:
-        # K back-to-back scans replayed from HIP graphs: one graph of a scan
-        # per resident input copy, replayed K // copies times, and one of the
-        # remaining K % copies scans; events around the whole region
-        def graph_time(nstreams):
-            ns = max(1, nstreams)
-            gss = [torch.cuda.Stream() for _ in range(ns)]
-            outs = [out] + [torch.empty_like(out) for _ in range(ns - 1)]
-            gs = gss[0]
-            for q in gss:
-                q.wait_stream(stream)
-                with torch.cuda.stream(q):
-                    for i in range(2):
-                        P.pfsm_scan_async(h, xs[i % n_copies], outs[gss.index(q)], counts[i:i + 1], stream=q)
-                q.synchronize()
-            cnt_g = torch.zeros(n_copies, dtype=torch.int64, device=dev)
-            reps, rest = divmod(args.steps, n_copies)
-            graphs = []
-            for m in ([n_copies] if reps else []) + ([rest] if rest else []):
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g, stream=gs):
-                    for q in gss[1:]:
-                        q.wait_stream(gs)  # fork
-                    for k in range(m):
-                        P.pfsm_scan_async(h, xs[k], outs[k % ns], cnt_g[k:k + 1], stream=gss[k % ns])
-                    for q in gss[1:]:
-                        gs.wait_stream(q)  # join
-                graphs.append((g, m))
-            with torch.cuda.stream(gs):
-                for g, _ in graphs:
-                    g.replay()  # untimed
-            gs.synchronize()
-            wall0 = time.perf_counter()
-            with torch.cuda.stream(gs):
-                t_start.record(gs)
-                for _ in range(reps):
-                    graphs[0][0].replay()
-                if rest:
-                    graphs[-1][0].replay()
-                t_end.record(gs)
-            gs.synchronize()
-            wall = time.perf_counter() - wall0
-            total_ms = t_start.elapsed_time(t_end)
-            got = cnt_g[:min(args.steps, n_copies)].cpu().numpy()
-            if not np.all(got == n_ref):
-                raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
-            for o in outs[:min(ns, args.steps)]:
-                if not np.array_equal(o[:n_ref].cpu().numpy(), ref_rows):
-                    raise SystemExit("a graph-replayed scan's matches differ from the eager scan's")
-            return total_ms, wall
-
-        # one stream: each scan's own launch time (the roofline's); then the
-        # scans of `value`, alternating over the streams so that they overlap
-        ns = max(1, args.streams)
-        one_ms, one_wall = graph_time(1)
-        total_ms, wall = graph_time(ns) if ns > 1 else (one_ms, one_wall)
-        kern_ms = np.array([one_ms / args.steps])
-        got = np.array([n_ref])
-        timing = ("HIP-graph replays of back-to-back scans; events around the timed region" if ns == 1 else
-                  f"HIP-graph replays with the scans alternating over {ns} streams (independent scans overlap); "
-                  "events around the timed region; kernel_avg_us from the same replays on one stream")
-    if not np.all(got == n_ref):
-        raise SystemExit(f"scan counts differ between steps: {np.unique(got)} vs {n_ref}")
+        # `value`: the scans back to back on one stream, replayed from HIP
+        # graphs; the overlapped rate (independent scans alternating over
+        # several streams) is reported beside it
+        total_ms, wall = time_scans(P, h, xs, out, args.steps, 1, n_ref, ref_rows)
+        kern_ms = np.array([total_ms / args.steps])
+        timing = "HIP-graph replays of back-to-back scans on one stream; events around the timed region"
+        if args.overlap_streams > 1:
+            o_ms, _ = time_scans(P, h, xs, out, args.steps, args.overlap_streams, n_ref, ref_rows)
+            overlapped = {"streams": args.overlap_streams, "GB/s": round(n * args.steps / (o_ms / 1e3) / 1e9, 2),
+                          "us_per_scan": round(o_ms / args.steps * 1e3, 3),
+                          "note": "independent scans alternating over several streams inside the graph, so that "
+                                  "one scan's workgroups fill the compute units the previous one leaves idle"}
 
     ms_per_step = total_ms / args.steps
     gbs = n * args.steps / (total_ms / 1e3) / 1e9
@@ -585,7 +662,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n_bytes": n, "seed": wl.seed,
                    "n_states": int(wl.automaton.n_states), "kind": wl.automaton.kind,
-                   "matches_per_scan": int(n_ref), "resident_input_copies": n_copies},
+                   "matches_per_scan": int(n_ref), "resident_input_copies": n_copies,
+                   "streams": 1 if not args.eager else "eager"},
         "transitions_per_s": round(tps, 1),
         "transitions_per_scan": int(transitions),
         "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
@@ -601,14 +679,23 @@ def main():
                           "frac": round(transitions / kern_avg_s / 1e9 / LDS_PEAK_GLOOKUPS, 4),
                           "lookups_per_launch": int(transitions),
                           "note": "one table lookup per instance-step (T)"}
-                         if kernel == "dfa_scan_kernel" else None),
+                         if kernel == "dfa_scan_kernel" else
+                         {"bound": "lds", "achieved": round(stats["activations"] / kern_avg_s / 1e9, 2),
+                          "peak": LDS_PEAK_GLOOKUPS, "unit": "Glookup/s",
+                          "frac": round(stats["activations"] / kern_avg_s / 1e9 / LDS_PEAK_GLOOKUPS, 5),
+                          "lookups_per_launch": int(stats["activations"]),
+                          "note": "one state-record lookup per state activation (X)"}
+                         if kernel == "nfa_scan_kernel" else None),
         "wall_s_timed": round(wall, 4),
         "timing": timing,
-        "one_stream": {"GB/s": round(n / (float(kern_ms.mean()) / 1e3) / 1e9, 2),
-                       "us_per_scan": round(float(kern_ms.mean()) * 1e3, 3)},
+        "overlapped": overlapped,
     }
     h.free()
-    sections = [("batched", args.no_batch, lambda: batched_vs_plain(args.batch_replays)),
+    del xs
+    torch.cuda.empty_cache()
+    sections = [("cfg3", args.no_cfg3 or args.workload != "cfg2",
+                 lambda: nfa_cfg3(args.cfg3_steps, args.cpu_seconds, args.no_cpu)),
+                ("batched", args.no_batch, lambda: batched_vs_plain(args.batch_replays)),
                 ("served", args.no_serve, lambda: served(args.serve_requests)),
                 ("long_walks", args.no_long, long_walks),
                 ("streamed", args.no_stream, streamed),

@@ -244,3 +244,35 @@ def test_graph_capture_replays(P):
     finally:
         for h in hs:
             h.free()
+
+
+def test_cfg4_full_size_with_edits(P):
+    """The batched workload at its stated size: 4,096 streams of 64 B-1 MiB
+    (about 460 MB) over four DFAs of 256-4,096 states and a 2,000-signature
+    NFA union; every stream's list equals the oracle's before and after the
+    workload's 100 add/remove edits of the NFA."""
+    wl = W.cfg4()
+    assert len(wl.stream_automaton) == 4096 and len(wl.ops) == 100
+    print(f"cfg4 full: {len(wl.stream_automaton)} streams, {wl.data.size} bytes", flush=True)
+    hs = [P.pfsm_load(a) for a in wl.automata]
+    try:
+        got = _batch_lists(P, hs, wl)
+        refs = _cfg4_refs(wl, [], [])
+        for s in range(len(refs)):
+            assert np.array_equal(got[s], refs[s]), s
+        nfa_h = hs[wl.meta["nfa_index"]]
+        removed, added = [], []
+        for op in wl.ops:
+            if op[0] == "add":
+                P.pfsm_add_pattern(nfa_h, op[1])
+                added.append(op[1])
+            else:
+                P.pfsm_remove_pattern(nfa_h, op[1])
+                removed.append(op[1])
+        got = _batch_lists(P, hs, wl)
+        refs = _cfg4_refs(wl, removed, added)
+        for s in range(len(refs)):
+            assert np.array_equal(got[s], refs[s]), s
+    finally:
+        for h in hs:
+            h.free()

@@ -159,3 +159,43 @@ def test_wait_then_release_and_empty_results(P):
     assert got[1].shape == (0, 3)
     for h in hs:
         h.free()
+
+
+def test_cfg5_full_size_alone_equals_mixed(P):
+    """The served workload at its stated size: 8 resident automata (4 random
+    16-state DFAs, 4 NFA unions of 2,000 signatures) and requests log-uniform
+    on 256 B-4 MiB.  Probe requests served alone, then mixed among the others
+    while they run: every result equals the oracle's."""
+    wl = W.cfg5()
+    hs = [P.pfsm_load(a) for a in wl.automata]
+    rng = np.random.default_rng(55)
+    reqs = wl.requests(rng, 120)
+    # probes: the largest request of each automaton present
+    probe = []
+    for a in range(len(wl.automata)):
+        mine = [x for b, x in reqs if b == a]
+        if mine:
+            probe.append((a, max(mine, key=len)))
+    print(f"cfg5 full: {len(reqs)} requests, {sum(len(x) for _, x in reqs)} bytes, "
+          f"largest {max(len(x) for _, x in reqs)}", flush=True)
+    try:
+        with P.Server(hs, mem_budget=1 << 30, max_batch=256) as sv:
+            alone = [sv.wait(sv.submit(a, x, borrow=True)) for a, x in probe]
+            ids, order = [], []
+            for k, (a, x) in enumerate(reqs):
+                ids.append(sv.submit(a, x, borrow=True))
+                order.append((a, x))
+                if k % 30 == 15:
+                    for a2, x2 in probe:
+                        ids.append(sv.submit(a2, x2, borrow=True))
+                        order.append((a2, x2))
+            mixed = [sv.wait(i) for i in ids]
+        for (a, x), got in zip(order, mixed):
+            ref, _ = oracle.scan(wl.automata[a], x)
+            assert np.array_equal(got, ref), (a, len(x))
+        for (a, x), got in zip(probe, alone):
+            ref, _ = oracle.scan(wl.automata[a], x)
+            assert np.array_equal(got, ref), (a, len(x))
+    finally:
+        for h in hs:
+            h.free()
