@@ -168,6 +168,24 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
 int pfsm_scan_async(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
                     int64_t cap, int64_t *d_n_matches, void *hip_stream);
 
+/* pfsm_scan_async for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the call allocates nothing, neither device nor host memory.  Its scratch
+ * (the scan's control block, look-back words, per-workgroup counters and
+ * parked walks) is one static array of about 32.3 MiB in the library's
+ * global memory, one copy per GPU, held until the process ends.  The first
+ * call on a GPU clears the array's control words on `hip_stream`.
+ *   Arguments, output and total as for pfsm_scan_async; DFA handles only.
+ *   The scan uses at most 512 workgroups and 32768 segments: an input that
+ *   the handle's segment size splits into more segments is rejected.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (concurrent streams, or host threads) race and must be serialised by
+ * the caller.  pfsm_last_stats does not report these scans.
+ * Errors: PFSM_EINVAL (arguments, or more than 32768 segments), PFSM_ENOSYS
+ * (NFA handle), PFSM_EHIP.                                                 */
+int pfsm_scan_noalloc(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
+                      int64_t *d_n_matches, void *hip_stream);
+
 /* Scan many byte streams, each against one of several handles, in one pass:
  * the union model of Section III.A applied per stream (each stream's
  * matches are those of pfsm_scan of its bytes alone against its handle).

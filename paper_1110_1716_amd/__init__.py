@@ -10,7 +10,7 @@ missing, loading fails loudly -- there is no fallback.
 
 Names follow the C ABI: ``pfsm_load_dfa``, ``pfsm_load_nfa``,
 ``pfsm_add_pattern``, ``pfsm_remove_pattern``, ``pfsm_scan``,
-``pfsm_scan_async``, ``pfsm_scan_batch``, ``pfsm_scan_batch_async``, ``pfsm_last_stats``,
+``pfsm_scan_async``, ``pfsm_scan_noalloc``, ``pfsm_scan_batch``, ``pfsm_scan_batch_async``, ``pfsm_last_stats``,
 ``pfsm_free``; ``Stream`` wraps ``pfsm_stream_*`` and ``Server`` ``pfsm_server_*``.
 """
 from __future__ import annotations
@@ -51,7 +51,7 @@ EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pa
            "pfsm_server_wait",
            "pfsm_server_times", "pfsm_server_release", "pfsm_server_stats_get", "pfsm_server_destroy",
            "pfsm_stream_open", "pfsm_stream_feed", "pfsm_stream_info", "pfsm_stream_close",
-           "pfsm_set_option", "pfsm_get_option", "pfsm_tune", "pfsm_release_cached")
+           "pfsm_set_option", "pfsm_get_option", "pfsm_tune", "pfsm_release_cached", "pfsm_scan_noalloc")
 
 
 class PfsmError(RuntimeError):
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
         "pfsm_remove_pattern": (ctypes.c_int, [vp, i32, vp]),
         "pfsm_scan": (ctypes.c_int, [vp, vp, i64, vp, i64, ctypes.POINTER(i64), vp]),
         "pfsm_scan_async": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, vp]),
+        "pfsm_scan_noalloc": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, vp]),
         "pfsm_scan_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, i32, vp, i64, vp,
                                            ctypes.POINTER(i64), vp]),
         "pfsm_scan_batch_async": (ctypes.c_int, [vp, i32, vp, vp, vp, i32, vp, i64, vp, vp]),
@@ -305,6 +306,17 @@ def pfsm_scan_async(h: Pfsm, x, out, d_n_matches, stream=None) -> None:
         raise PfsmError(PFSM_EINVAL, "d_n_matches must be an int64 CUDA tensor")
     _check(load_library().pfsm_scan_async(h.ptr, x.data_ptr(), x.numel(), out.data_ptr(), out.shape[0],
                                           d_n_matches.data_ptr(), _stream_ptr(stream)))
+
+
+def pfsm_scan_noalloc(h: Pfsm, x, out, d_n_matches, stream=None) -> None:
+    """pfsm_scan_async through the entry point that allocates nothing (DFA handles)."""
+    import torch
+    _check_input(x)
+    _check_out(out)
+    if not (isinstance(d_n_matches, torch.Tensor) and d_n_matches.is_cuda and d_n_matches.dtype == torch.int64):
+        raise PfsmError(PFSM_EINVAL, "d_n_matches must be an int64 CUDA tensor")
+    _check(load_library().pfsm_scan_noalloc(h.ptr, x.data_ptr(), x.numel(), out.data_ptr(), out.shape[0],
+                                            d_n_matches.data_ptr(), _stream_ptr(stream)))
 
 
 def pfsm_scan_batch(handles, data, stream_off, stream_automaton, out=None, match_off=None, stream=None,

@@ -429,16 +429,11 @@ int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream) {
     return dfa_upload_caches(h, s);
 }
 
-// One launch of the DFA scan kernel: a single stream (plan == nullptr) or the
-// segments of a batch plan.
-static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
-                      int64_t cap, int64_t *d_total, hipStream_t s, const int64_t *d_base = nullptr,
-                      const CarryOut *carry = nullptr) {
-    Workspace *w;
-    int rc = h->pool.get(s, h->n_blocks, &w);
-    if (rc) return rc;
-    if (!w->spill) HIP_TRY(hipMalloc(&w->spill, (size_t)h->n_blocks * kDfaSpill * 16));
-    DfaArgs a;
+// The fields of a DFA scan launch that come from the handle and the call:
+// input, tables, output and the LDS layout.  The caller sets the scratch
+// fields (ctl, lb, bstats, spill) and the segment plan.
+static void dfa_common_args(const pfsm_t *h, const uint8_t *x, int64_t n, MatchOut *out, int64_t cap,
+                            int64_t *d_total, DfaArgs &a) {
     std::memset(&a, 0, sizeof a);
     a.x = x;
     a.n = n;
@@ -457,6 +452,27 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
     a.out = out;
     a.cap = cap;
     a.total = d_total;
+    a.off_flags = h->off_flags;
+    a.off_laboff = h->off_laboff;
+    a.off_lab = h->off_lab;
+    a.off_tab = h->off_tab;
+    a.off_q = h->off_q;
+    a.off_m = h->off_m;
+    a.off_list = h->off_list;
+    a.lds_bytes = h->lds_bytes;
+}
+
+// One launch of the DFA scan kernel: a single stream (plan == nullptr) or the
+// segments of a batch plan.
+static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *plan, int64_t seg, MatchOut *out,
+                      int64_t cap, int64_t *d_total, hipStream_t s, const int64_t *d_base = nullptr,
+                      const CarryOut *carry = nullptr) {
+    Workspace *w;
+    int rc = h->pool.get(s, h->n_blocks, &w);
+    if (rc) return rc;
+    if (!w->spill) HIP_TRY(hipMalloc(&w->spill, (size_t)h->n_blocks * kDfaSpill * 16));
+    DfaArgs a;
+    dfa_common_args(h, x, n, out, cap, d_total, a);
     a.ctl = w->ctl;
     a.bstats = w->bstats;
     a.spill = w->spill;
@@ -478,14 +494,6 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
     // after any growth of the look-back words above
     a.lb = w->lb;
     a.lb_cap = w->lb_cap;
-    a.off_flags = h->off_flags;
-    a.off_laboff = h->off_laboff;
-    a.off_lab = h->off_lab;
-    a.off_tab = h->off_tab;
-    a.off_q = h->off_q;
-    a.off_m = h->off_m;
-    a.off_list = h->off_list;
-    a.lds_bytes = h->lds_bytes;
     // A plain scan places its segments' matches after the scan (dfa_defer.h).
     DfaDefer d;
     std::memset(&d, 0, sizeof d);
@@ -590,6 +598,116 @@ int pfsm_scan(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out,
     *n_matches = *reinterpret_cast<volatile int64_t *>(w->h_total);
     if (*n_matches > cap)
         return fail(PFSM_EOVERFLOW, "%lld matches, capacity %lld", (long long)*n_matches, (long long)cap);
+    return PFSM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------- scan without allocation
+
+namespace {
+
+// Scratch of pfsm_scan_noalloc, one copy per GPU in the module's own global
+// memory: the scan's control block, its look-back words, the per-workgroup
+// counters and the walks a workgroup parks out of LDS.  Sized for at most
+// kNaBlocks workgroups and kNaSegs segments (about 32.3 MiB).
+constexpr int kNaBlocks = 512;
+constexpr int kNaSegs = kMaxSegs;
+constexpr int kNaLbWords = kNaSegs + kNaBlocks;
+constexpr size_t kNaOffLb = 256;  // after the ScanCtl
+constexpr size_t kNaOffStats = kNaOffLb + (size_t)kNaLbWords * sizeof(unsigned long long);
+constexpr size_t kNaOffSpill = (kNaOffStats + (size_t)kNaBlocks * 4 * sizeof(long long) + 255) / 256 * 256;
+constexpr size_t kNaBytes = kNaOffSpill + (size_t)kNaBlocks * kDfaSpill * 16;
+static_assert(sizeof(ScanCtl) <= kNaOffLb, "control block overlaps the look-back words");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Zero the control block and the look-back words (the counters and the
+// parked walks are written before they are read).
+__global__ void noalloc_clear_kernel(unsigned long long *p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Per device: the device address of `scratch` (hipGetSymbolAddress) and
+// whether its control words have been cleared.
+constexpr int kNaMaxDevices = 64;
+struct NaDevice {
+    unsigned char *ptr = nullptr;
+    bool cleared = false;
+};
+std::mutex g_na_mu;
+NaDevice g_na[kNaMaxDevices];
+
+// Set-up on the current device, once: look up the scratch address and clear
+// its control words on `s`, ahead of the first scan.
+int noalloc_scratch(hipStream_t s, unsigned char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(PFSM_EINVAL, "device %d beyond the %d supported", dev, kNaMaxDevices);
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    NaDevice &d = g_na[dev];
+    if (!d.ptr) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        d.ptr = static_cast<unsigned char *>(p);
+    }
+    if (!d.cleared) {
+        const int64_t words = (int64_t)(kNaOffStats / sizeof(unsigned long long));
+        hipLaunchKernelGGL(noalloc_clear_kernel, dim3(64), dim3(256), 0, s,
+                           reinterpret_cast<unsigned long long *>(d.ptr), words);
+        HIP_TRY(hipGetLastError());
+        d.cleared = true;
+    }
+    *out = d.ptr;
+    return PFSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfsm_scan_noalloc(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t *d_out, int64_t cap,
+                      int64_t *d_n_matches, void *hip_stream) {
+    if (!h) return fail(PFSM_EINVAL, "NULL handle");
+    if (h->kind != 0) return fail(PFSM_ENOSYS, "the scan without allocation takes DFA handles");
+    if (n < 0 || n > kMaxStream) return fail(PFSM_EINVAL, "n must be in [0, 2^31 - 16]");
+    if (cap < 0) return fail(PFSM_EINVAL, "cap must be >= 0");
+    if (!d_n_matches) return fail(PFSM_EINVAL, "d_n_matches is NULL");
+    if (n > 0 && !d_input) return fail(PFSM_EINVAL, "d_input is NULL");
+    if (cap > 0 && !d_out) return fail(PFSM_EINVAL, "d_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int blocks = std::min(h->n_blocks, kNaBlocks);
+    int64_t seg = 0;
+    int rounds = 0;
+    if (n > 0)
+        plan_segments(n, blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax, kDfaSegFloor, &seg, &rounds);
+    const int64_t n_segs = n > 0 ? (n + seg - 1) / seg : 0;
+    if (n_segs > kNaSegs)
+        return fail(PFSM_EINVAL, "%lld segments of %lld bytes exceed the %d the scratch holds (raise the segment size)",
+                    (long long)n_segs, (long long)seg, kNaSegs);
+    unsigned char *base = nullptr;
+    int rc = noalloc_scratch(s, &base);
+    if (rc) return rc;
+    if (n == 0) {
+        HIP_TRY(launch_write_zero(d_n_matches, s));
+        return PFSM_OK;
+    }
+    DfaArgs a;
+    dfa_common_args(h, d_input, n, reinterpret_cast<MatchOut *>(d_out), cap, d_n_matches, a);
+    a.ctl = reinterpret_cast<ScanCtl *>(base);
+    a.lb = reinterpret_cast<unsigned long long *>(base + kNaOffLb);
+    a.lb_cap = kNaLbWords;
+    a.bstats = reinterpret_cast<long long *>(base + kNaOffStats);
+    a.spill = base + kNaOffSpill;
+    a.seg = seg;
+    a.n_segs = (int32_t)n_segs;
+    // Matches go straight to their places: no staging rows.
+    DfaDefer d;
+    std::memset(&d, 0, sizeof d);
+    const int grid = (int)std::min<int64_t>(n_segs, blocks);
+    void *args[] = {&a, &d};
+    HIP_TRY(hipLaunchKernel(h->kernel, dim3(grid), dim3(kDfaThreads), args, h->lds_bytes, s));
     return PFSM_OK;
 }
 
