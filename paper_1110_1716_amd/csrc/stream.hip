@@ -18,13 +18,14 @@
 //   6. after one synchronisation (the match total and the pair count): the
 //      carry pairs become sorted unique keys grouped by start, the carried
 //      set of the next piece (one workgroup sorts a few thousand pairs in
-//      LDS; more go through a device-wide radix sort).
+//      LDS; more are sorted in LDS tiles of 2048 keys, then merged pairwise
+//      in passes over device memory).
 // The stream state changes only when a piece succeeds, so a piece refused
 // for lack of output room can be fed again with a larger buffer.
-#include <hipcub/hipcub.hpp>
-
+#include <algorithm>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "host_common.h"
 #include "pfsm.h"
@@ -76,11 +77,6 @@ __global__ void shift_kernel(MatchOut *out, const int64_t *lo, const int64_t *hi
     }
 }
 
-__global__ void keys_kernel(const uint32_t *pairs, int64_t m, unsigned long long *keys) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        keys[i] = ((unsigned long long)pairs[2 * i] << 32) | pairs[2 * i + 1];
-}
-
 // Sorted keys to unique keys and the offsets of their start groups.
 __global__ __launch_bounds__(ST) void compact_kernel(const unsigned long long *sorted, int64_t m,
                                                      unsigned long long *keys, int32_t *grp_off, int32_t *n_groups) {
@@ -107,21 +103,15 @@ __global__ __launch_bounds__(ST) void compact_kernel(const unsigned long long *s
     }
 }
 
-// Sort, deduplicate and group at most kSmallCarry pairs in one workgroup
-// (bitonic sort of the keys in LDS), for the usual case of a few carried
-// instances: one launch instead of a device-wide sort.
-constexpr int kSmallCarry = 2048;
+__device__ __forceinline__ unsigned long long pair_key(const uint32_t *pairs, int64_t i) {
+    return ((unsigned long long)pairs[2 * i] << 32) | pairs[2 * i + 1];
+}
 
-__global__ __launch_bounds__(ST) void small_carry_kernel(const uint32_t *pairs, int m, unsigned long long *keys,
-                                                         int32_t *grp_off, int32_t *n_groups) {
-    __shared__ unsigned long long k_s[kSmallCarry];
-    __shared__ long long red[ST / 64];
+// Bitonic sort of np keys in LDS (np a power of two, at most 2048), by the
+// whole workgroup.  Keys are below 2^63 (starts below 2^31), so the ~0
+// padding sorts last.
+__device__ __forceinline__ void bitonic_lds(unsigned long long *k_s, int np) {
     const int tid = threadIdx.x;
-    int np = 1;
-    while (np < m) np <<= 1;
-    for (int i = tid; i < np; i += ST)
-        k_s[i] = i < m ? ((unsigned long long)pairs[2 * i] << 32) | pairs[2 * i + 1] : ~0ull;
-    __syncthreads();
     for (int size = 2; size <= np; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = tid; i < np; i += ST) {
@@ -137,6 +127,23 @@ __global__ __launch_bounds__(ST) void small_carry_kernel(const uint32_t *pairs, 
             }
             __syncthreads();
         }
+}
+
+// Sort, deduplicate and group at most kSmallCarry pairs in one workgroup
+// (bitonic sort of the keys in LDS), for the usual case of a few carried
+// instances: one launch.
+constexpr int kSmallCarry = 2048;
+
+__global__ __launch_bounds__(ST) void small_carry_kernel(const uint32_t *pairs, int m, unsigned long long *keys,
+                                                         int32_t *grp_off, int32_t *n_groups) {
+    __shared__ unsigned long long k_s[kSmallCarry];
+    __shared__ long long red[ST / 64];
+    const int tid = threadIdx.x;
+    int np = 1;
+    while (np < m) np <<= 1;
+    for (int i = tid; i < np; i += ST) k_s[i] = i < m ? pair_key(pairs, i) : ~0ull;
+    __syncthreads();
+    bitonic_lds(k_s, np);
     long long run_u = 0, run_g = 0;
     for (int c0 = 0; c0 < m; c0 += ST) {
         const int i = c0 + tid;
@@ -156,6 +163,53 @@ __global__ __launch_bounds__(ST) void small_carry_kernel(const uint32_t *pairs, 
     if (tid == 0) {
         grp_off[run_g] = (int32_t)run_u;
         *n_groups = (int32_t)run_g;
+    }
+}
+
+// More carry pairs: each workgroup sorts one tile of kSmallCarry keys in
+// LDS and writes its valid keys back in order.
+__global__ __launch_bounds__(ST) void tile_sort_kernel(const uint32_t *pairs, int64_t m, unsigned long long *dst) {
+    __shared__ unsigned long long k_s[kSmallCarry];
+    const int64_t t0 = (int64_t)blockIdx.x * kSmallCarry;
+    const int cnt = m - t0 < kSmallCarry ? (int)(m - t0) : kSmallCarry;
+    for (int i = threadIdx.x; i < kSmallCarry; i += ST) k_s[i] = i < cnt ? pair_key(pairs, t0 + i) : ~0ull;
+    __syncthreads();
+    bitonic_lds(k_s, kSmallCarry);
+    for (int i = threadIdx.x; i < cnt; i += ST) dst[t0 + i] = k_s[i];
+}
+
+// One merge pass: sorted runs of `width` keys (the last one shorter) are
+// merged in pairs.  A key's place in the merged run is its index in its own
+// run plus the number of keys of the other run that precede it, found by
+// binary search; on equal keys the left run's come first.  Every key moves
+// on its own, so the pass needs no synchronisation.
+__global__ __launch_bounds__(256) void merge_pass_kernel(const unsigned long long *src, unsigned long long *dst,
+                                                         int64_t m, int64_t width) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lo = i / (2 * width) * (2 * width);
+        const int64_t mid = lo + width < m ? lo + width : m;
+        const int64_t end = lo + 2 * width < m ? lo + 2 * width : m;
+        const unsigned long long k = src[i];
+        int64_t a, b;
+        if (i < mid) {  // left run: right keys strictly smaller
+            a = mid;
+            b = end;
+            while (a < b) {
+                const int64_t h = (a + b) >> 1;
+                if (src[h] < k) a = h + 1;
+                else b = h;
+            }
+            dst[i + (a - mid)] = k;
+        } else {  // right run: left keys smaller or equal
+            a = lo;
+            b = mid;
+            while (a < b) {
+                const int64_t h = (a + b) >> 1;
+                if (src[h] <= k) a = h + 1;
+                else b = h;
+            }
+            dst[lo + (i - mid) + (a - lo)] = k;
+        }
     }
 }
 
@@ -194,10 +248,8 @@ struct pfsm_stream {
     uint32_t *pairs = nullptr;
     int64_t c_pairs = 0;
     int64_t *d_back = nullptr;  // [2]: match total, carry pairs asked for (read back together)
-    unsigned long long *sort_in = nullptr, *sort_out = nullptr;
+    unsigned long long *sort_in = nullptr, *sort_out = nullptr;  // merge passes alternate between them
     int64_t c_sort_in = 0, c_sort_out = 0;
-    void *sort_tmp = nullptr;
-    size_t c_sort_tmp = 0;
     int64_t *cnt = nullptr, *off = nullptr;
     int64_t c_cnt = 0, c_off = 0;
     int64_t *d_r = nullptr;
@@ -208,7 +260,7 @@ struct pfsm_stream {
             if (keys[i]) (void)hipFree(keys[i]);
             if (grp[i]) (void)hipFree(grp[i]);
         }
-        void *dev[] = {n_groups, pairs, d_back, sort_in, sort_out, sort_tmp, cnt, off, d_r};
+        void *dev[] = {n_groups, pairs, d_back, sort_in, sort_out, cnt, off, d_r};
         for (void *p : dev)
             if (p) (void)hipFree(p);
         if (h_back) (void)hipHostFree(h_back);
@@ -309,21 +361,17 @@ int pfsm_stream_feed(pfsm_stream_t *st, const uint8_t *d_piece, int64_t n, pfsm_
                            st->n_groups + nx);
         HIP_TRY(hipGetLastError());
     } else {
-        hipLaunchKernelGGL(keys_kernel, dim3(256), dim3(256), 0, s, st->pairs, m, st->sort_in);
+        const int64_t tiles = (m + kSmallCarry - 1) / kSmallCarry;
+        hipLaunchKernelGGL(tile_sort_kernel, dim3((unsigned)tiles), dim3(ST), 0, s, st->pairs, m, st->sort_in);
         HIP_TRY(hipGetLastError());
-        size_t need = 0;
-        HIP_TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, need, st->sort_in, st->sort_out, (int)m, 0, 64, s));
-        if (need > st->c_sort_tmp) {
-            HIP_TRY(hipStreamSynchronize(s));
-            if (st->sort_tmp) HIP_TRY(hipFree(st->sort_tmp));
-            st->sort_tmp = nullptr;
-            st->c_sort_tmp = 0;
-            HIP_TRY(hipMalloc(&st->sort_tmp, need));
-            st->c_sort_tmp = need;
+        unsigned long long *src = st->sort_in, *dst = st->sort_out;
+        for (int64_t width = kSmallCarry; width < m; width *= 2) {
+            const int64_t grid = std::min<int64_t>((m + 255) / 256, 4096);
+            hipLaunchKernelGGL(merge_pass_kernel, dim3((unsigned)grid), dim3(256), 0, s, src, dst, m, width);
+            HIP_TRY(hipGetLastError());
+            std::swap(src, dst);
         }
-        size_t have = st->c_sort_tmp;
-        HIP_TRY(hipcub::DeviceRadixSort::SortKeys(st->sort_tmp, have, st->sort_in, st->sort_out, (int)m, 0, 64, s));
-        hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(ST), 0, s, st->sort_out, m, st->keys[nx], st->grp[nx],
+        hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(ST), 0, s, src, m, st->keys[nx], st->grp[nx],
                            st->n_groups + nx);
         HIP_TRY(hipGetLastError());
     }

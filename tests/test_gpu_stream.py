@@ -122,6 +122,30 @@ def test_sigma_plus_many_carried(P):
     assert len(ref) == n * (n + 1) // 2
 
 
+def test_many_carried_merge_passes(P):
+    # 30,000 live starts at the cut: 15 sorted tiles (the last ragged) and
+    # four merge passes before the carried set is compacted
+    from oracle import subset
+    rng = np.random.default_rng(18)
+    fsm = subset.to_dfa(regex_nfa([(b"[a-d]+e", 0)]))
+    abcd = np.frombuffer(b"abcd", np.uint8)
+    x = np.concatenate([rng.choice(abcd, 30000), np.frombuffer(b"eabce", np.uint8), rng.choice(abcd, 100)])
+    ref = check_stream(P, fsm, x, [30000, 30002])
+    assert len(ref) == 30003
+
+
+def test_many_carried_nfa_sets(P):
+    # every start carries several NFA states (and repeated pairs): 6,000
+    # starts whose sets go through the tile sort, the merges and the
+    # de-duplication
+    rng = np.random.default_rng(19)
+    nfa = regex_nfa([(b"[a-d]*e", 0), (b"[a-d]*ae", 1), (b"[a-c]*de", 2), (b"[a-d][a-d]*f", 3)])
+    abcd = np.frombuffer(b"abcd", np.uint8)
+    x = np.concatenate([rng.choice(abcd, 6000), np.frombuffer(b"aefde", np.uint8), rng.choice(abcd, 50)])
+    ref = check_stream(P, nfa, x, [6000, 6001, 6003], carried=None)
+    assert len(ref) > 12000
+
+
 def test_sigma_plus_nfa_every_start_carried(P):
     n = 700
     x = np.random.default_rng(15).integers(0, 256, n, dtype=np.uint8)
