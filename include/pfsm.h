@@ -131,21 +131,33 @@ int pfsm_load_dfa(pfsm_t **out, const pfsm_dfa_desc *d, void *hip_stream);
  * Errors: PFSM_EINVAL, PFSM_ENOMEM, PFSM_EHIP.                            */
 int pfsm_load_nfa(pfsm_t **out, const pfsm_nfa_desc *d, void *hip_stream);
 
-/* Add an expression to a loaded NFA handle without rebuilding it
- * (Section III.A: expressions can be added or removed efficiently;
- * Section IV: with zero downtime).  The pattern's automaton is put together
- * with the handle's through an ancillary initial state and an epsilon edge
- * (Section III.A).  Its labels must not occur in the handle.  Scans issued
- * before the call keep the old automaton; scans issued after it (on any
- * stream) see the new one.
+/* Add an expression to a loaded NFA handle (Section III.A: expressions can
+ * be added or removed efficiently; Section IV: with zero downtime).  The
+ * pattern's automaton is put together with the handle's through an
+ * ancillary initial state and an epsilon edge (Section III.A).  Its labels
+ * must not occur in the handle.  The edit is incremental: only the new
+ * pattern's tables are computed, the start tables are reassembled, and the
+ * changed ranges are copied into the handle's device buffers in place.
+ * Scans issued before the call keep the old automaton (the call waits for
+ * them); scans issued after it (on any stream) see the new one.
+ * HIP graphs: a graph that scans with this handle, captured while
+ * PFSM_OPT_LAYOUT_EPOCH had some value, sees the edited automaton when it
+ * is replayed after the edit as long as the epoch still has that value.
+ * When an edit outgrows the buffers, the epoch advances: the old buffers
+ * stay allocated (and unchanged) until pfsm_free, so such a graph still
+ * replays safely, but it scans the automaton of its capture; capture it
+ * again (after one pfsm_scan_batch on its stream, which sizes the stream's
+ * workspace for the larger automaton).
  * Errors: PFSM_EINVAL, PFSM_EEXIST (label already present), PFSM_ENOSYS
  * (DFA handle: its table is monolithic), PFSM_ENOMEM, PFSM_EHIP.          */
 int pfsm_add_pattern(pfsm_t *h, const pfsm_nfa_desc *pattern, void *hip_stream);
 
 /* Remove an expression: after the call no match with `label` is reported.
  * Patterns added with pfsm_add_pattern are cut off the ancillary initial
- * state; otherwise the label is disabled in the label table.  Same snapshot
- * semantics as pfsm_add_pattern.
+ * state; otherwise the label is disabled in the label table, and only the
+ * parts of the tables that lead to it are recomputed.  Tables only shrink,
+ * so they are rewritten in place and PFSM_OPT_LAYOUT_EPOCH stays (for DFA
+ * handles too).  Same snapshot and graph semantics as pfsm_add_pattern.
  * Errors: PFSM_ENOENT (label not present), PFSM_ENOMEM, PFSM_EHIP.        */
 int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream);
 
@@ -218,7 +230,9 @@ int pfsm_scan_batch(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data
  * and replayed.  The grand total is d_match_off[n_streams]; the caller
  * compares it with cap once the stream has reached it.  The device buffers
  * must already be large enough: run pfsm_scan_batch once on the same stream
- * with the same or larger sizes first (PFSM_ENOMEM otherwise).  A batch
+ * with the same or larger sizes first (PFSM_ENOMEM otherwise).  A captured
+ * graph sees later pattern edits of its handles while their
+ * PFSM_OPT_LAYOUT_EPOCH is unchanged (pfsm_add_pattern).  A batch
  * whose automaton indices or offsets are invalid reports 0 matches.
  * Errors: PFSM_EINVAL, PFSM_ENOMEM, PFSM_EHIP.                            */
 int pfsm_scan_batch_async(pfsm_t *const *hs, int32_t n_automata, const uint8_t *d_data,
@@ -248,10 +262,15 @@ enum {
                                          lookup per distinct active state, Section III.B) for single
                                          scans; 0 = one walk per start (default).  Batches and
                                          streams always walk per start.                            */
-    PFSM_OPT_MERGED_COUNT_LIMIT = 8   /* tag-merged stepping keeps per-start match counts and
+    PFSM_OPT_MERGED_COUNT_LIMIT = 8,  /* tag-merged stepping keeps per-start match counts and
                                          output offsets in 32 bits up to this value, and larger
                                          ones in 64 bits in memory: 0 = 2^31 - 1 (default); a small
                                          value exercises the memory paths (results are the same)  */
+    PFSM_OPT_LAYOUT_EPOCH = 9         /* read only: advances whenever an edit or a setting moves the
+                                         handle's device tables to new buffers or changes a value
+                                         its launches carry (the NFA pair cache turned on or off,
+                                         a DFA table budget); captured HIP graphs see later edits
+                                         only while it stays the same                              */
 };
 
 /* Set a writable option (table budget and pair cache rebuild the device

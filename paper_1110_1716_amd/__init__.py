@@ -43,6 +43,7 @@ PFSM_OPT_MAX_WORKGROUPS_PER_CU = 5
 PFSM_OPT_RESIDENT_TABLE = 6
 PFSM_OPT_MERGED_WALKS = 7
 PFSM_OPT_MERGED_COUNT_LIMIT = 8
+PFSM_OPT_LAYOUT_EPOCH = 9
 
 # Exported symbols of libpfsm.so, as declared in include/pfsm.h.
 EXPORTS = ("pfsm_load_dfa", "pfsm_load_nfa", "pfsm_add_pattern", "pfsm_remove_pattern", "pfsm_scan",

@@ -70,6 +70,21 @@ struct DevBuf {
     T *as() const {
         return static_cast<T *>(p);
     }
+    // Copies `count` elements into the buffer as it is (they must fit); the
+    // caller synchronises `s` before `src` dies.
+    template <typename T>
+    int write(const T *src, size_t count, hipStream_t s) {
+        if (count * sizeof(T) > bytes) return fail(PFSM_EINVAL, "cache outgrew its buffer");
+        if (count) HIP_TRY(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+        return PFSM_OK;
+    }
+    // Give up ownership of the buffer (the caller frees it later).
+    void *detach() {
+        void *q = p;
+        p = nullptr;
+        bytes = 0;
+        return q;
+    }
 };
 
 // Longest stream: positions, shifted by up to 15 bytes for alignment, are
@@ -112,8 +127,10 @@ struct Workspace {
     long long *defer_seg = nullptr;       //   per segment: first row, count, offset
     int64_t c_defer_seg = 0;
     unsigned long long *defer_cursor = nullptr;
+    std::vector<void *> retired;          // replay scratch outgrown by the union
 
     ~Workspace() {
+        for (void *p : retired) (void)hipFree(p);
         if (slots) (void)hipFree(slots);
         if (ctl) (void)hipFree(ctl);
         if (lb) (void)hipFree(lb);

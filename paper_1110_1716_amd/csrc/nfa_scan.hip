@@ -241,9 +241,10 @@ __device__ __forceinline__ int first_two(Ctx &c, int c1, int c2, uint32_t (&S)[K
     if (a.pair_on) {
         const int p = c1 * 256 + c2;
         if (!((c.pbits_s[p >> 5] >> (p & 31)) & 1u)) return 0;
-        const int s_lo = a.p_off[p], s_hi = a.p_off[p + 1];
-        pair_lab_lo = a.pl_off[p];
-        pair_lab_hi = a.pl_off[p + 1];
+        const PairRange r = a.p_rng[p];
+        const int s_lo = r.st_lo, s_hi = r.st_hi;
+        pair_lab_lo = r.lab_lo;
+        pair_lab_hi = r.lab_hi;
         const int cnt = s_hi - s_lo;
         if (cnt > K) {
             overflow = true;

@@ -214,12 +214,18 @@ struct __attribute__((aligned(16))) NfaRec {
     uint32_t e0_test, e0_tgt, e1_test, e1_tgt;
 };
 constexpr uint32_t kRecLive = 1, kRecFinal = 2, kRecInline = 4;
+
+// The lists of a byte pair in the pair cache: p_st[st_lo, st_hi) and
+// p_lab[lab_lo, lab_hi); one 16-byte load.
+struct __attribute__((aligned(16))) PairRange {
+    int32_t st_lo, st_hi, lab_lo, lab_hi;
+};
 constexpr uint32_t kTgtList = 1u << 31, kTgtFinal = 1u << 30, kStateMask = (1u << 30) - 1;
 
 struct NfaArgs {
     const uint8_t *x;  // 16-byte aligned
     int64_t n;
-    int32_t n_states;
+    int32_t n_states;           // state capacity of the tables: the replay scratch stride
     const NfaRec *rec;          // [n_states]
     const uint32_t *edges;      // (test, target) pairs for records with more than two edges
     const uint32_t *class_bits; // [n_classes * 8]
@@ -234,9 +240,8 @@ struct NfaArgs {
     // first two symbols (when pair_on): the same for the byte pair (c1, c2)
     int32_t pair_on;
     const uint32_t *p_bits;     // [2048] pair has states or labels
-    const int32_t *p_off;       // [65537]
-    const uint32_t *p_st;
-    const int32_t *pl_off;      // [65537]
+    const PairRange *p_rng;     // [65536] where each pair's lists lie
+    const uint32_t *p_st;       // target words
     const int32_t *p_lab;
     MatchOut *out;
     int64_t cap;
@@ -249,7 +254,8 @@ struct NfaArgs {
     long long *bstats;          // [gridDim.x * 4]
     int64_t seg;
     // per-workgroup replay scratch: two frontiers of n_states entries and a
-    // bitset of n_states bits (all clear between uses)
+    // bitset of n_states bits (all clear between uses); state ids are below
+    // n_states
     uint32_t *big_front;        // [gridDim.x * 2 * n_states]
     uint32_t *big_bits;         // [gridDim.x * ((n_states + 31) / 32)]
     CarryOut carry;             // live instances at the end of the input

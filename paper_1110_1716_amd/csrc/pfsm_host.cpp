@@ -71,6 +71,16 @@ struct pfsm {
     WorkspacePool pool;
     // ---- successful edits (streams opened before an edit refuse to go on)
     uint64_t edits = 0;
+    // ---- DFA: device buffers replaced by a new layout (freed with the
+    // handle, since captured graphs may still refer to them) and the count
+    // of such replacements
+    std::vector<void *> retired;
+    uint64_t layout_epoch = 0;
+    bool laid_out = false;
+
+    ~pfsm() {
+        for (void *p : retired) (void)hipFree(p);
+    }
 };
 
 namespace {
@@ -108,7 +118,10 @@ int align16(int v) { return (v + 15) & ~15; }
 // live flags (reverse search from states with an enabled label over
 // transitions some byte can take), the q0 row per byte, the LDS copies of the
 // rows of q0's successors, label CSR; then the LDS layout and grid size.
-int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
+// With `in_place` (after a label is removed) the layout stays as it is and
+// the caches that change are rewritten inside their buffers: the label area
+// only shrinks, and neither the table nor its cached rows depend on labels.
+int dfa_upload_caches(pfsm_t *h, hipStream_t s, bool in_place = false) {
     const int32_t N = h->n_states, S = h->n_symbols;
     std::vector<std::vector<int32_t>> en(N);
     for (int32_t q = 0; q < N; ++q)
@@ -150,6 +163,48 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     for (int32_t q = 0; q < N; ++q) {
         lab.insert(lab.end(), en[q].begin(), en[q].end());
         off[q + 1] = (int32_t)lab.size();
+    }
+
+    if (in_place) {
+        const bool resident = h->enc == kEnc8 || h->enc == kEnc8D || h->enc == kEnc16;
+        if ((int64_t)lab.size() * 4 > (int64_t)h->d_lab.bytes ||
+            (resident && (int64_t)lab.size() * 4 > h->off_tab - h->off_lab))
+            return fail(PFSM_EINVAL, "label area outgrown");
+        int rc;
+        if ((rc = h->d_first.write(first.data(), 256, s))) return rc;
+        if ((rc = h->d_flags.write(flags.data(), N, s))) return rc;
+        if ((rc = h->d_lab_off.write(off.data(), N + 1, s))) return rc;
+        if (!lab.empty() && (rc = h->d_lab.write(lab.data(), lab.size(), s))) return rc;
+        std::vector<uint8_t> head;
+        if (resident) {
+            head.assign((size_t)(h->off_tab - h->off_flags), 0);
+            std::memcpy(head.data(), flags.data(), (size_t)N);
+            std::memcpy(head.data() + (h->off_laboff - h->off_flags), off.data(), sizeof(int32_t) * (size_t)(N + 1));
+            if (!lab.empty())
+                std::memcpy(head.data() + (h->off_lab - h->off_flags), lab.data(), sizeof(int32_t) * lab.size());
+            if ((rc = h->d_res.write(head.data(), head.size(), s))) return rc;
+        }
+        std::vector<uint8_t> mt;
+        if (h->merged_ok) {
+            mt.resize((size_t)N * 256);
+            for (int32_t q = 0; q < N; ++q)
+                for (int b = 0; b < 256; ++b) {
+                    const int sy = h->b2s[b];
+                    const int32_t v = sy < 0 ? -1 : h->delta[(int64_t)q * S + sy];
+                    const bool ok = v >= 0 && (flags[v] & kLive);
+                    mt[(size_t)q * 256 + b] = ok ? (uint8_t)(v | ((flags[v] & kFinal) ? 128 : 0)) : 255;
+                }
+            if ((rc = h->d_mtab.write(mt.data(), mt.size(), s))) return rc;
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        return PFSM_OK;
+    }
+    // A new layout: buffers a captured graph may still name are kept.
+    if (h->laid_out) {
+        DevBuf *old[] = {&h->d_first, &h->d_first_slot, &h->d_res, &h->d_flags, &h->d_lab_off, &h->d_lab, &h->d_mtab};
+        for (DevBuf *b : old)
+            if (b->p) h->retired.push_back(b->detach());
+        ++h->layout_epoch;
     }
 
     // An automaton over a byte map whose byte-indexed 8-bit table fits LDS
@@ -278,6 +333,7 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s) {
     h->enc = enc;
     h->n_hot = n_hot;
     h->res_bytes = (int32_t)img.size();
+    h->laid_out = true;
 
     h->dev_identity = h->identity || (expand && SD == 256);
     h->dev_symbols = SD;
@@ -423,10 +479,10 @@ int pfsm_remove_pattern(pfsm_t *h, int32_t label, void *hip_stream) {
     if (!found) return fail(PFSM_ENOENT, "no final state carries label %d", label);
     h->disabled.insert(std::upper_bound(h->disabled.begin(), h->disabled.end(), label), label);
     // Scans already issued read the current caches: wait for the device,
-    // then replace the caches.
+    // then rewrite them in place.
     HIP_TRY(hipDeviceSynchronize());
     ++h->edits;
-    return dfa_upload_caches(h, s);
+    return dfa_upload_caches(h, s, true);
 }
 
 // The fields of a DFA scan launch that come from the handle and the call:
@@ -774,6 +830,9 @@ int pfsm_get_option(const pfsm_t *h, int32_t option, int64_t *value) {
         return PFSM_OK;
     case PFSM_OPT_MERGED_WALKS: *value = k->merged; return PFSM_OK;
     case PFSM_OPT_MERGED_COUNT_LIMIT: *value = k->merged_lim; return PFSM_OK;
+    case PFSM_OPT_LAYOUT_EPOCH:
+        *value = (int64_t)(h->kind == 1 ? nfa_layout_epoch(h->nfa.get()) : h->layout_epoch);
+        return PFSM_OK;
     case PFSM_OPT_RESIDENT_TABLE:
         if (h->kind == 1) return fail(PFSM_ENOSYS, "the table encoding applies to DFA handles");
         *value = (h->enc == kEnc8 || h->enc == kEnc8D || h->enc == kEnc16) ? 1 : 0;

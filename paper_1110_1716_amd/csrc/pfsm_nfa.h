@@ -36,6 +36,9 @@ int nfa_resume(NfaHost *h, const uint8_t *x, int64_t n, int32_t base, const Carr
 int nfa_grid_blocks(NfaHost *h);
 Knobs *nfa_knobs(NfaHost *h);
 int nfa_occupancy(NfaHost *h);
+// Advances whenever an edit or option moves the handle's device tables or
+// changes a scalar its launches carry.
+uint64_t nfa_layout_epoch(NfaHost *h);
 // After a change of h's knobs: the grid, and the tables when `tables`.
 int nfa_apply_knobs(NfaHost *h, bool tables, hipStream_t s);
 WorkspacePool *nfa_pool(NfaHost *h);

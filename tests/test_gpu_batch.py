@@ -276,3 +276,99 @@ def test_cfg4_full_size_with_edits(P):
     finally:
         for h in hs:
             h.free()
+
+
+def test_graph_replay_sees_edits_until_the_layout_moves(P):
+    """A batch captured in a HIP graph, then NFA adds/removes and a DFA label
+    removal that fit the handles' buffers: the layout epoch stays and every
+    replay equals the oracle of the edited automata.  An add that outgrows
+    the NFA's buffers advances its epoch: the old graph still replays its
+    (unchanged) old buffers, an eager batch sees the new pattern, and a graph
+    captured again does too."""
+    from oracle import compose
+    wl = W.cfg4(seed=47, n_streams=60, len_hi=1 << 15, n_patterns=100, n_ops=8)
+    hs = [P.pfsm_load(a) for a in wl.automata]
+    nfa_i = wl.meta["nfa_index"]
+    nfa_h = hs[nfa_i]
+    # a label of the 256-state DFA (table resident in LDS) and of the
+    # 4,096-state one (table read through L2)
+    dfa_labs = {0: int(np.asarray(wl.automata[0].final_labels)[0]),
+                3: int(np.asarray(wl.automata[3].final_labels)[-1])}
+    try:
+        s = torch.cuda.Stream()
+        d = torch.from_numpy(wl.data.copy()).cuda()
+        so = torch.from_numpy(wl.stream_off).cuda()
+        sa = torch.from_numpy(wl.stream_automaton).cuda()
+        cap = wl.data.size // 16 + 1024
+        n_s = len(wl.stream_automaton)
+        with torch.cuda.stream(s):
+            out_g = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+            mo_g = torch.empty(n_s + 1, dtype=torch.int64, device="cuda")
+            P.pfsm_scan_batch(hs, d, so, sa, stream=s)
+        s.synchronize()
+
+        def capture():
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                P.pfsm_scan_batch_async(hs, d, so, sa, out_g, mo_g, stream=s)
+            return g
+
+        def replay_lists(g):
+            out_g.fill_(-1)
+            mo_g.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got, mo = out_g.cpu().numpy(), mo_g.cpu().numpy()
+            return [got[mo[i]:mo[i + 1]] for i in range(n_s)]
+
+        def refs_for(removed, added, dfa_removed):
+            refs = _cfg4_refs(wl, removed, added)
+            for i in range(n_s):
+                a = int(wl.stream_automaton[i])
+                if a in dfa_labs and dfa_removed:
+                    refs[i] = compose.drop_label(refs[i], dfa_labs[a])
+            return refs
+
+        def same(lists, refs):
+            for i in range(n_s):
+                assert np.array_equal(lists[i], refs[i]), i
+
+        g = capture()
+        same(replay_lists(g), refs_for([], [], False))
+        e_nfa = P.pfsm_get_option(nfa_h, P.PFSM_OPT_LAYOUT_EPOCH)
+        e_dfa = {a: P.pfsm_get_option(hs[a], P.PFSM_OPT_LAYOUT_EPOCH) for a in dfa_labs}
+        removed, added = [], []
+        for op in wl.ops:
+            if op[0] == "add":
+                P.pfsm_add_pattern(nfa_h, op[1])
+                added.append(op[1])
+            else:
+                P.pfsm_remove_pattern(nfa_h, op[1])
+                removed.append(op[1])
+        for a, lab in dfa_labs.items():
+            P.pfsm_remove_pattern(hs[a], lab)
+        assert P.pfsm_get_option(nfa_h, P.PFSM_OPT_LAYOUT_EPOCH) == e_nfa
+        for a in dfa_labs:
+            assert P.pfsm_get_option(hs[a], P.PFSM_OPT_LAYOUT_EPOCH) == e_dfa[a]
+        edited = refs_for(removed, added, True)
+        for rep in range(2):
+            same(replay_lists(g), edited)
+            P.pfsm_scan_batch(hs, d, so, sa, stream=s)  # eager work between replays
+            torch.cuda.synchronize()
+
+        # an add far larger than the union so far: the NFA's buffers move
+        big = W.union_nfa(W.signature_union(np.random.default_rng(48), 300, label_base=5000))
+        P.pfsm_add_pattern(nfa_h, big)
+        assert P.pfsm_get_option(nfa_h, P.PFSM_OPT_LAYOUT_EPOCH) > e_nfa
+        same(replay_lists(g), edited)  # the old buffers, as they were
+        grown = refs_for(removed, added + [big], True)
+        n, got, mo = P.pfsm_scan_batch(hs, d, so, sa, stream=s)
+        got, mo = got.cpu().numpy(), mo.cpu().numpy()
+        same([got[mo[i]:mo[i + 1]] for i in range(n_s)], grown)
+        del g
+        g2 = capture()
+        same(replay_lists(g2), grown)
+    finally:
+        for h in hs:
+            h.free()
