@@ -369,7 +369,11 @@ def pfsm_scan_batch(handles, data, stream_off, stream_automaton, out=None, match
 def pfsm_scan_batch_async(handles, data, stream_off, stream_automaton, out, match_off, stream=None) -> None:
     """Enqueue a batch with no host round trip (capturable in a HIP graph);
     the total is match_off[n_streams].  Buffers must have been sized by a
-    pfsm_scan_batch call of the same or larger size on the same stream."""
+    pfsm_scan_batch call of the same or larger size on the same stream.
+    A captured graph sees later pattern edits of its handles while their
+    PFSM_OPT_LAYOUT_EPOCH option is unchanged; after it changes, the graph
+    still replays safely but scans the automaton of before the change:
+    run pfsm_scan_batch once and capture again."""
     _check_input(data)
     _check_out(out)
     arr = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
