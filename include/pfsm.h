@@ -297,8 +297,9 @@ typedef struct {
  * (table budget or pair cache), then the workgroups per compute unit, then
  * the segment size, each timed over
  * `reps` scans, and keep each change that saves at least 2 %.  Every
- * setting must reproduce the sample's match count, else PFSM_EINVAL (the
- * settings are then unspecified).  Allocates its own output buffer;
+ * setting must reproduce the sample's match list of the starting settings,
+ * entry by entry, else PFSM_EINVAL (the settings are then unspecified).
+ * Allocates its own output buffer and a host copy of the list;
  * synchronises `hip_stream`.  Errors: PFSM_EINVAL, PFSM_ENOMEM, PFSM_EHIP. */
 int pfsm_tune(pfsm_t *h, const uint8_t *d_sample, int64_t n, int32_t reps, pfsm_tune_report *report,
               void *hip_stream);

@@ -8,10 +8,11 @@
 //
 // Settings are tried one knob at a time, each on a scan of a caller's
 // sample timed with HIP events, and a change is kept when it saves at least
-// 2 %.  Every setting must reproduce the match count of the first one:
-// knobs change where work runs, never what is found.
+// 2 %.  Every setting must reproduce the match list of the first one, entry
+// by entry: knobs change where work runs, never what is found.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <vector>
 
 #include "host_common.h"
@@ -32,6 +33,7 @@ struct Timer {
     hipStream_t s;
     hipEvent_t e0, e1;
     int tried = 0;
+    std::vector<pfsm_match_t> ref, cur;  // the first setting's list, the latest one
 
     // Mean time per scan (ms) under the handle's current settings.
     int time(double *ms) {
@@ -50,6 +52,11 @@ struct Timer {
         if (got != count)
             return fail(PFSM_EINVAL, "a tuning setting changed the match count (%lld, expected %lld)", (long long)got,
                         (long long)count);
+        std::vector<pfsm_match_t> &dst = tried == 0 ? ref : cur;
+        dst.resize((size_t)count);
+        if (count > 0) HIP_TRY(hipMemcpy(dst.data(), out, sizeof(pfsm_match_t) * (size_t)count, hipMemcpyDeviceToHost));
+        if (tried > 0 && count > 0 && std::memcmp(ref.data(), dst.data(), sizeof(pfsm_match_t) * (size_t)count) != 0)
+            return fail(PFSM_EINVAL, "a tuning setting changed the match list");
         *ms = (double)t / reps;
         ++tried;
         return PFSM_OK;
