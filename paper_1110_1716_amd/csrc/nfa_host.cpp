@@ -413,6 +413,38 @@ int compute_comp(NfaHost *h, int32_t ci, bool place) {
             n_edge += (int32_t)es.size();
         }
     }
+    // Gap states: a run of consecutive ids q, q + 1, ... each passing any
+    // byte to the next and sharing one other edge E, the last with E alone
+    // (a bounded .{0,m} gap before E).  Marked from the highest id down, so
+    // that the remaining length of the next state is known.
+    {
+        auto is_any = [](uint32_t t) { return ((t >> 8) & 3u) == 1u; };
+        std::vector<int32_t> rem(n, -1);
+        for (int32_t i = n - 1; i >= 0; --i) {
+            NfaRec &r = recs[i];
+            if (!live[i] || !en[i].empty() || !(r.info & kRecInline)) continue;
+            if (r.n_edges == 1) {
+                if (!is_any(r.e0_test)) rem[i] = 0;  // may end a gap
+                continue;
+            }
+            if (r.n_edges != 2 || i + 1 >= n || S[i + 1] != S[i] + 1 || rem[i + 1] < 0) continue;
+            const uint32_t next = (uint32_t)S[i + 1];
+            int ai = -1;
+            if (is_any(r.e1_test) && r.e1_tgt == next) ai = 1;
+            else if (is_any(r.e0_test) && r.e0_tgt == next) ai = 0;
+            if (ai < 0) continue;
+            const uint32_t et = ai == 1 ? r.e0_test : r.e1_test, eg = ai == 1 ? r.e0_tgt : r.e1_tgt;
+            const NfaRec &nr = recs[i + 1];  // its e0 is its E (ends and marked gap states)
+            if (is_any(et) || nr.e0_test != et || nr.e0_tgt != eg) continue;
+            r.e0_test = et;
+            r.e0_tgt = eg;
+            r.e1_test = 1u << 8;
+            r.e1_tgt = next;
+            r.info |= kRecGap;
+            r.edge_off = rem[i + 1] + 1;
+            rem[i] = rem[i + 1] + 1;
+        }
+    }
     // regions: new ones at the ends; old ones must hold the new tables
     if (place) {
         c.list_at = list_at;

@@ -493,24 +493,26 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
     }
     __builtin_amdgcn_wave_barrier();
     uint4 ch[QK];
-    int steps[QK];
+    int32_t cend[QK];  // end of the walk's chunk (or of the input)
 #pragma unroll
     for (int j = 0; j < QK; ++j) {
-        steps[j] = 0;
+        cend[j] = 0;
         ch[j] = make_uint4(0, 0, 0, 0);
         if (alive[j]) {
             const int64_t c0 = (int64_t)(e[j].pos & ~15);
             ch[j] = load_granule(c.xa, c0);
             ++c.L;
-            steps[j] = (int)((c0 + 16 < c.nP ? c0 + 16 : c.nP) - e[j].pos);
+            cend[j] = (int32_t)(c0 + 16 < c.nP ? c0 + 16 : c.nP);
         }
     }
+    // Each pass consumes at least one byte of every active walk, so 16
+    // passes finish the chunk.
     for (int st = 0; st < 16; ++st) {
         bool act[QK];
         bool any = false;
 #pragma unroll
         for (int j = 0; j < QK; ++j) {
-            act[j] = alive[j] && st < steps[j];
+            act[j] = alive[j] && e[j].pos < cend[j];
             any |= act[j];
         }
         if (!__any(any)) break;
@@ -523,6 +525,24 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
 #pragma unroll
         for (int j = 0; j < QK; ++j) {
             if (!act[j]) continue;
+            if (e[j].n == 1 && (r[j][0].info & kRecGap)) {
+                // A lone gap state: every byte its other edge rejects moves
+                // it one state along the gap (one instance-step, one live
+                // state, no report), while any-byte steps remain.  Only the
+                // walk's chunk is read: loads past it, one lane at a time,
+                // cost more than the queue's next round.
+                const int32_t lim = (int32_t)min((int64_t)cend[j], (int64_t)e[j].pos + r[j][0].edge_off);
+                int32_t p = e[j].pos;
+                while (p < lim && !edge_matches(a, r[j][0].e0_test, byte_of(ch[j], p & 15))) ++p;
+                const int32_t skip = p - e[j].pos;
+                if (skip > 0) {
+                    c.T += skip;
+                    c.X += skip;
+                    e[j].s[0] += (uint32_t)skip;
+                    e[j].pos = p;
+                    continue;
+                }
+            }
             uint32_t O[K];
             int nO;
             if (!nfa_step_rec(a, r[j], e[j].n, byte_of(ch[j], e[j].pos & 15), O, nO)) {

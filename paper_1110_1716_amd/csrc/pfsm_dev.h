@@ -213,7 +213,14 @@ struct __attribute__((aligned(16))) NfaRec {
     int32_t n_edges;
     uint32_t e0_test, e0_tgt, e1_test, e1_tgt;
 };
-constexpr uint32_t kRecLive = 1, kRecFinal = 2, kRecInline = 4;
+constexpr uint32_t kRecLive = 1, kRecFinal = 2, kRecInline = 4, kRecGap = 8;
+// A gap state (kRecGap) is a state of a bounded any-byte gap: state q with
+// exactly two inline edges, e0 = an edge E and e1 = any byte to q + 1, where
+// q + 1 carries the same E and either continues the gap the same way or
+// ends it with E alone.  edge_off holds how many any-byte steps remain
+// (at least 1).  A walk whose whole set is one gap state can pass every byte
+// that E rejects, up to that many, without reading records: each such byte
+// moves it to the next state of the gap.
 
 // The lists of a byte pair in the pair cache: p_st[st_lo, st_hi) and
 // p_lab[lab_lo, lab_hi); one 16-byte load.
