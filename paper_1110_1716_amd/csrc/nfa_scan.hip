@@ -531,7 +531,8 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
                 // state, no report), while any-byte steps remain.  Only the
                 // walk's chunk is read: loads past it, one lane at a time,
                 // cost more than the queue's next round.
-                const int32_t lim = (int32_t)min((int64_t)cend[j], (int64_t)e[j].pos + r[j][0].edge_off);
+                const int32_t room = cend[j] - e[j].pos;  // compared first: pos + edge_off may not fit 32 bits
+                const int32_t lim = r[j][0].edge_off < room ? e[j].pos + r[j][0].edge_off : cend[j];
                 int32_t p = e[j].pos;
                 while (p < lim && !edge_matches(a, r[j][0].e0_test, byte_of(ch[j], p & 15))) ++p;
                 const int32_t skip = p - e[j].pos;
