@@ -538,7 +538,8 @@ static int dfa_launch(pfsm_t *h, const uint8_t *x, int64_t n, const SegPlan *pla
         a.seg = seg;
     } else {
         int rounds;
-        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax, kDfaSegFloor, &a.seg,
+        plan_segments(n, h->n_blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax,
+                      dfa_seg_floor(n, h->res_bytes), &a.seg,
                       &rounds);
         const int64_t n_segs = (n + a.seg - 1) / a.seg;
         if ((rc = grow_lb(w, (int)n_segs))) return rc;
@@ -737,7 +738,8 @@ int pfsm_scan_noalloc(pfsm_t *h, const uint8_t *d_input, int64_t n, pfsm_match_t
     int64_t seg = 0;
     int rounds = 0;
     if (n > 0)
-        plan_segments(n, blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax, kDfaSegFloor, &seg, &rounds);
+        plan_segments(n, blocks, h->knobs.segment > 0 ? h->knobs.segment : kDfaSegMax, dfa_seg_floor(n, h->res_bytes),
+                      &seg, &rounds);
     const int64_t n_segs = n > 0 ? (n + seg - 1) / seg : 0;
     if (n_segs > kNaSegs)
         return fail(PFSM_EINVAL, "%lld segments of %lld bytes exceed the %d the scratch holds (raise the segment size)",
