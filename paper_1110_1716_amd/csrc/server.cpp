@@ -165,13 +165,18 @@ struct Slot {
     int64_t bytes = 0;    // input bytes of this batch
     int64_t out_cap = 0;  // output rows reserved for it
     Buf h_data{nullptr, 0, true}, h_off{nullptr, 0, true}, h_aut{nullptr, 0, true}, h_moff{nullptr, 0, true},
-        h_out{nullptr, 0, true}, h_info{nullptr, 0, true}, h_lohi{nullptr, 0, true};
+        h_info{nullptr, 0, true}, h_lohi{nullptr, 0, true};
+    // The batch copies its whole output reservation to the host in stream
+    // order, into one of two pinned buffers: the next batch of the slot uses
+    // the other one while this one's results are copied out to the callers.
+    Buf h_out[2] = {{nullptr, 0, true}, {nullptr, 0, true}};
+    int hk = 0;  // the buffer of the batch in flight
     Buf d_data, d_off, d_aut, d_moff, d_out;
     BatchRun run;
 
     void release() {
-        for (Buf *b : {&h_data, &h_off, &h_aut, &h_moff, &h_out, &h_info, &h_lohi, &d_data, &d_off, &d_aut, &d_moff,
-                       &d_out})
+        for (Buf *b : {&h_data, &h_off, &h_aut, &h_moff, &h_out[0], &h_out[1], &h_info, &h_lohi, &d_data, &d_off,
+                       &d_aut, &d_moff, &d_out})
             b->release();
         if (ev) (void)hipEventDestroy(ev);
         if (stream) (void)hipStreamDestroy(stream);
@@ -261,6 +266,7 @@ struct pfsm_server {
         if ((rc = sl.h_aut.reserve(4 * nr))) return rc;
         if ((rc = sl.d_aut.reserve(4 * nr))) return rc;
         if ((rc = sl.d_out.reserve(sl.out_cap * (int64_t)sizeof(MatchOut)))) return rc;
+        if ((rc = sl.h_out[sl.hk].reserve(std::max<int64_t>(sl.out_cap, 1) * (int64_t)sizeof(MatchOut)))) return rc;
         if ((rc = sl.h_info.reserve(sizeof(BatchInfo)))) return rc;
         const int64_t t0 = now_ns();
         int64_t pos = 0;
@@ -285,6 +291,9 @@ struct pfsm_server {
             return rc;
         HIP_TRY(hipMemcpyAsync(sl.h_moff.p, sl.d_moff.p, 8 * (nr + 1), hipMemcpyDeviceToHost, sl.stream));
         HIP_TRY(hipMemcpyAsync(sl.h_info.p, sl.run.info, sizeof(BatchInfo), hipMemcpyDeviceToHost, sl.stream));
+        if (sl.out_cap > 0)
+            HIP_TRY(hipMemcpyAsync(sl.h_out[sl.hk].p, sl.d_out.p, sl.out_cap * (int64_t)sizeof(MatchOut),
+                                   hipMemcpyDeviceToHost, sl.stream));
         HIP_TRY(hipEventRecord(sl.ev, sl.stream));
         std::lock_guard<std::mutex> lk(mu);
         ++st.batches;
@@ -321,14 +330,8 @@ struct pfsm_server {
             for (int64_t j = 0; j < nr; ++j) whole[j] = mo[j + 1] <= sl.out_cap && hi[j] <= sl.run.stage_cap;
         }
         const int64_t t0 = now_ns();
-        const int64_t got = std::min(total, sl.out_cap);
-        if ((rc = sl.h_out.reserve(std::max<int64_t>(got, 1) * (int64_t)sizeof(pfsm_match_t)))) return rc;
-        if (got) {
-            HIP_TRY(hipMemcpyAsync(sl.h_out.p, sl.d_out.p, got * sizeof(pfsm_match_t), hipMemcpyDeviceToHost,
-                                   sl.stream));
-            HIP_TRY(hipStreamSynchronize(sl.stream));
-        }
-        const pfsm_match_t *m = sl.h_out.as<pfsm_match_t>();
+        // the batch's output rows, min(total, out_cap), are in h_out[hk]
+        const pfsm_match_t *m = sl.h_out[sl.hk].as<pfsm_match_t>();
         std::vector<Req *> redo;
         std::vector<Req *> done;
         std::vector<std::tuple<void *, const void *, int64_t>> parts;
@@ -367,6 +370,7 @@ struct pfsm_server {
         inflight -= charge(bytes, sl.out_cap);
         sl.reqs.clear();
         sl.busy = false;
+        sl.hk ^= 1;  // the results being copied out stay in the other buffer
         if (admit(sl)) {
             sl.busy = true;
             const int lrc = launch(sl);
