@@ -444,6 +444,37 @@ int compute_comp(NfaHost *h, int32_t ci, bool place) {
             r.edge_off = rem[i + 1] + 1;
             rem[i] = rem[i + 1] + 1;
         }
+        // Gap states whose E leads into a simple chain: from E's target on,
+        // every state passes exactly one edge to a plain state (its epsilon
+        // closure is itself) and is not final, up to a last state with no
+        // edge, which is final.  The attempts E starts at different bytes
+        // then never share a state, and each reports only at the chain's end.
+        // Such a record (never final itself) keeps the chain's first edge
+        // test in lab_off.
+        for (int32_t i = 0; i < n; ++i) {
+            NfaRec &r = recs[i];
+            if (!(r.info & kRecGap) || (r.e0_tgt & kTgtList)) continue;
+            uint32_t t0 = 0;
+            bool ok = false;
+            int32_t q = (int32_t)(r.e0_tgt & kStateMask);
+            for (int32_t len = 0; len <= n; ++len) {
+                if (h->comp_of[q] != ci) break;
+                const int32_t j = loc(q);
+                const NfaRec &u = recs[j];
+                if (!live[j] || !(u.info & kRecInline) || (u.info & kRecGap)) break;
+                const bool fin = !en[j].empty();
+                if (u.n_edges == 0) {
+                    ok = fin;
+                    break;
+                }
+                if (fin || u.n_edges != 1 || (u.e0_tgt & kTgtList)) break;
+                if (len == 0) t0 = u.e0_test;
+                q = (int32_t)(u.e0_tgt & kStateMask);
+            }
+            if (!ok) continue;
+            r.info |= kRecGapFin;
+            r.lab_off = (int32_t)t0;
+        }
     }
     // regions: new ones at the ends; old ones must hold the new tables
     if (place) {

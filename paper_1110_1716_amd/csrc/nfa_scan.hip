@@ -51,6 +51,15 @@ struct Big {
     int32_t start, k0, pos0, pad;
 };
 
+// A walk whose whole set is one gap state marked kRecGapFin, waiting for a
+// gap pass (next symbol at pos, k matches reported so far; at most 64
+// any-byte steps left).
+struct GapEnt {
+    int32_t start, pos, k;
+    uint32_t g;
+};
+constexpr int GC = kNfaGapCap;
+
 // Where a walk's matches go.
 enum Mode : int { kBuffer = 0, kCount = 1, kWrite = 2 };
 
@@ -478,8 +487,175 @@ __device__ __forceinline__ long long walk_block(Ctx &c, int32_t s, int32_t k0, i
 // the workgroup's replay list.  A lane's walks advance together, one symbol
 // each per step, and the state records of all of them are requested before
 // any is used, so their L2 round trips overlap.
+// An edge test prepared for many bytes: a byte, any byte, or a class
+// bitmap read through the cache.
+struct ByteTest {
+    uint32_t kind, val;
+    const uint32_t *cls;
+};
+__device__ __forceinline__ ByteTest byte_test(const NfaArgs &a, uint32_t test) {
+    const uint32_t kind = (test >> 8) & 3u;
+    return ByteTest{kind, test & 255u, kind == 2 ? a.class_bits + (size_t)(test >> 10) * 8 : nullptr};
+}
+__device__ __forceinline__ uint32_t test_byte(const ByteTest &t, int b) {
+    if (t.kind == 0) return (uint32_t)b == t.val ? 1u : 0u;
+    if (t.kind == 1) return 1u;
+    return (t.cls[b >> 5] >> (b & 31)) & 1u;
+}
+
+// Bits [lo, hi] of a 128-bit mask (h0: bits 0-63, h1: 64-127); empty when
+// hi < lo.
+__device__ __forceinline__ void range_bits(int lo, int hi, unsigned long long &h0, unsigned long long &h1) {
+    auto upto = [](int x) -> unsigned long long {  // bits [0, x) of a 64-bit word, x in [0, 64]
+        return x <= 0 ? 0ull : (x >= 64 ? ~0ull : (1ull << x) - 1ull);
+    };
+    h0 = upto(hi + 1) & ~upto(lo);
+    h1 = upto(hi + 1 - 64) & ~upto(lo - 64);
+}
+
+// Report the labels of final state w (a target word) at `end`.
 template <class Ctx>
-__device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *big_s, int *nbig) {
+__device__ __forceinline__ void emit_state(Ctx &c, uint32_t w, int32_t start, int32_t end, int32_t &k) {
+    const NfaRec r = c.a.rec[w & kStateMask];
+    const int hi = r.lab_off + (int)(r.info >> 8);
+    int last = -1;
+    for (int l = r.lab_off; l < hi; ++l) {
+        const int lab = c.a.lab[l];
+        if (lab <= last) continue;
+        c.put(kBuffer, start, end, lab, k, 0);
+        ++k;
+        last = lab;
+    }
+}
+
+// Gap pass: up to 64 waiting gap walks, one per lane, each finished at once.
+// From a lone gap state g with r any-byte steps left at position pos, the
+// instance holds the next gap state after each of the symbols pos .. pos +
+// r - 1, and each symbol p in [pos, pos + r] that E accepts starts an
+// attempt along the chain after E.  Attempts started at different symbols
+// are at different chain states at any time (the chain is simple), so the
+// set sizes add up: X gains the gap states plus every attempt's length, the
+// instance lives until the latest of them ends (T counts up to the symbol
+// after it), and attempts that reach the chain's final end report, in order
+// of their first symbol (which is also the order of their ends).  The
+// bytes of [pos, pos + 80] come from six 16-byte loads issued together; E
+// and the chain's first edge are tested on all of them, and only attempts
+// that pass both read on.
+template <class Ctx>
+__device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount) {
+    const NfaArgs &a = c.a;
+    const int lane = lane_id();
+    const int take = gcount < 64 ? gcount : 64;
+    const bool act = lane < take;
+    GapEnt g{0, 0, 0, 0u};
+    if (act) g = gl[lane];
+    __builtin_amdgcn_wave_barrier();
+    for (int e = 64 + lane; e < gcount; e += 64) gl[e - 64] = gl[e];
+    __builtin_amdgcn_wave_barrier();
+    gcount -= take;
+    if (!act) return;
+    const int32_t n = c.n32, pos = g.pos;
+    const int32_t base = pos & ~15;
+    const NfaRec gr = a.rec[g.g & kStateMask];
+    uint4 G0, G1, G2, G3, G4, G5;
+    {
+        const uint4 z = make_uint4(0, 0, 0, 0);
+        G0 = base < c.nP ? load_granule(c.xa, base) : z;
+        G1 = base + 16 < c.nP ? load_granule(c.xa, base + 16) : z;
+        G2 = base + 32 < c.nP ? load_granule(c.xa, base + 32) : z;
+        G3 = base + 48 < c.nP ? load_granule(c.xa, base + 48) : z;
+        G4 = base + 64 < c.nP ? load_granule(c.xa, base + 64) : z;
+        G5 = base + 80 < c.nP ? load_granule(c.xa, base + 80) : z;
+        c.L += 6;
+    }
+    const int32_t rr = gr.edge_off;  // any-byte steps left, at least 1
+    const uint32_t u0 = gr.e0_tgt;
+    const bool end0 = (u0 & kTgtFinal) != 0;  // E's target ends the chain
+    const ByteTest tE = byte_test(a, gr.e0_test);
+    const ByteTest tT = byte_test(a, end0 ? (1u << 8) : (uint32_t)gr.lab_off);
+    // hE: E accepts the byte at offset o from base; hT: the chain's first
+    // edge accepts it.  The granules move down one register per chunk.
+    unsigned long long hE0 = 0, hE1 = 0, hT0 = 0, hT1 = 0;
+#pragma unroll 1
+    for (int t = 0; t < 6; ++t) {
+        const uint4 v = G0;
+        G0 = G1;
+        G1 = G2;
+        G2 = G3;
+        G3 = G4;
+        G4 = G5;
+        uint32_t e16 = 0, t16 = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int b = byte_of(v, k);
+            e16 |= test_byte(tE, b) << k;
+            t16 |= test_byte(tT, b) << k;
+        }
+        const int sh = 16 * (t & 3);
+        if (t < 4) {
+            hE0 |= (unsigned long long)e16 << sh;
+            hT0 |= (unsigned long long)t16 << sh;
+        } else {
+            hE1 |= (unsigned long long)e16 << sh;
+            hT1 |= (unsigned long long)t16 << sh;
+        }
+    }
+    // Attempts start at [pos, pe]; a second chain state needs one more byte.
+    const int32_t pe = pos + rr < n - 1 ? pos + rr : n - 1;
+    unsigned long long w0, w1, v0, v1;
+    range_bits(pos - base, pe - base, w0, w1);
+    range_bits(pos - base, (pe < n - 2 ? pe : n - 2) - base, v0, v1);
+    const unsigned long long s0 = hE0 & w0, s1 = hE1 & w1;  // attempts
+    long long X = (rr < n - pos ? rr : n - pos) + __popcll(s0) + __popcll(s1);
+    int32_t last = (pos + rr - 1 < n - 1 ? pos + rr - 1 : n - 1);  // the last gap state's symbol
+    const int32_t top1 = s1 ? base + 127 - __clzll(s1) : (s0 ? base + 63 - __clzll(s0) : -1);
+    last = top1 > last ? top1 : last;
+    int32_t k = g.k;
+    if (end0) {
+        // E's target is the chain's end: every attempt reports at once.
+        for (int h = 0; h < 2; ++h)
+            for (unsigned long long m = h ? s1 : s0; m; m &= m - 1) {
+                const int32_t p = base + 64 * h + (__ffsll((long long)m) - 1);
+                emit_state(c, u0, g.start, p, k);
+            }
+    } else {
+        // Attempts whose second state is entered (the byte after the first
+        // passes the chain's first edge).
+        const unsigned long long d0 = s0 & v0 & ((hT0 >> 1) | (hT1 << 63)), d1 = s1 & v1 & (hT1 >> 1);
+        X += __popcll(d0) + __popcll(d1);
+        if (d0 | d1) {
+            const uint32_t u1 = a.rec[u0 & kStateMask].e0_tgt;
+            for (int h = 0; h < 2; ++h)
+                for (unsigned long long m = h ? d1 : d0; m; m &= m - 1) {
+                    const int32_t p = base + 64 * h + (__ffsll((long long)m) - 1);
+                    // The attempt holds u at symbol t; it ends at the
+                    // chain's final end or when a byte fails (or the input
+                    // ends).
+                    uint32_t u = u1;
+                    int32_t t = p + 1;
+                    for (;;) {
+                        if (u & kTgtFinal) {
+                            emit_state(c, u, g.start, t, k);
+                            break;
+                        }
+                        if (t + 1 >= n) break;
+                        const NfaRec ru = a.rec[u & kStateMask];
+                        if (!edge_matches(a, ru.e0_test, c.xa[t + 1])) break;
+                        ++X;
+                        u = ru.e0_tgt;
+                        ++t;
+                    }
+                    last = t > last ? t : last;
+                }
+        }
+    }
+    c.X += X;
+    c.T += (last - pos + 2 < n - pos ? last - pos + 2 : n - pos);
+}
+
+template <class Ctx>
+__device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *big_s, int *nbig, GapEnt *gl,
+                                            int &gcount) {
     const NfaArgs &a = c.a;
     const int lane = lane_id();
     Walk e[QK];
@@ -522,6 +698,20 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
 #pragma unroll
             for (int t = 0; t < K; ++t)
                 if (act[j] && t < e[j].n) r[j][t] = a.rec[e[j].s[t] & kStateMask];
+        if constexpr (!Ctx::kCarryOn) {
+            // A lone gap state whose gap ends in a simple chain waits for a
+            // gap pass instead, once at most 64 any-byte steps remain.
+#pragma unroll
+            for (int j = 0; j < QK; ++j) {
+                const bool fin = act[j] && e[j].n == 1 && (r[j][0].info & kRecGapFin) && r[j][0].edge_off <= 64;
+                const int slot = wave_push_slot(gcount, fin);
+                if (fin) {
+                    gl[slot] = GapEnt{e[j].start, e[j].pos, e[j].k, e[j].s[0]};
+                    act[j] = false;
+                    alive[j] = false;
+                }
+            }
+        }
 #pragma unroll
         for (int j = 0; j < QK; ++j) {
             if (!act[j]) continue;
@@ -572,6 +762,9 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
     }
     __builtin_amdgcn_wave_barrier();
     qcount = nc;
+    // A round adds at most QW gap walks, so fewer than 64 must wait after it.
+    if constexpr (!Ctx::kCarryOn)
+        while (gcount >= 64) gap_pass(c, gl, gcount);
 }
 
 template <bool kCarry>
@@ -587,6 +780,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     __shared__ int32_t mend[MC];
     __shared__ int32_t mlab[MC];
     __shared__ Big big_s[BC];
+    __shared__ GapEnt gap_all[kCarry ? 1 : (NT / 64) * GC];
     __shared__ int mn, ovf, nbig, seg_s, last_s, nsegs_s, segbase_s;
     __shared__ int sh[16];
     __shared__ long long red[NT / 64];
@@ -643,6 +837,8 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     constexpr bool cy = kCarry;
     Walk *q = qall + wv * QW;
     uint32_t *lst = lst_all + wv * 512;
+    GapEnt *gl = kCarry ? gap_all : gap_all + wv * GC;
+    int gcount = 0;
 
     // Replay every listed start with the whole workgroup.
     auto run_big = [&]() __attribute__((always_inline)) {
@@ -669,7 +865,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         const int pending = nbig;
         __syncthreads();
         if (pending > BC / 2) {
-            while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig);
+            while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
             run_big();
         }
     };
@@ -775,7 +971,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                             c.carry_first(i, c1);
                         }
                     }
-                    while (qcount > QW - 64) drain_round(c, q, qcount, big_s, &nbig);
+                    while (qcount > QW - 64) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
                     const int slot = wave_push_slot(qcount, push);
                     if (push) q[slot] = ent;
                 }
@@ -783,7 +979,9 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
             }
             replay_if_full(qcount);
         }
-        while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig);
+        while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
+        if constexpr (!kCarry)
+            while (gcount > 0) gap_pass(c, gl, gcount);
         __syncthreads();
         if (nbig > BC) {
             // more starts overflowed than the list holds: the whole segment

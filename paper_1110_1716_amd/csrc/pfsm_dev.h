@@ -196,6 +196,7 @@ constexpr int kNfaK = 4;                     // states a queued walk keeps in re
 constexpr int kNfaQueue = 64;                // walk queue entries per wave
 constexpr int kNfaMatchCap = 1024;           // LDS match buffer per workgroup
 constexpr int kNfaBigCap = 256;              // replayed starts listed per workgroup
+constexpr int kNfaGapCap = 192;              // gap walks waiting for a gap pass, per wave
 constexpr int kNfaLabelsMax = 1 << 24;       // labels per state
 
 // Packed state record, one 32-byte load per state and step.  Only live
@@ -213,7 +214,7 @@ struct __attribute__((aligned(16))) NfaRec {
     int32_t n_edges;
     uint32_t e0_test, e0_tgt, e1_test, e1_tgt;
 };
-constexpr uint32_t kRecLive = 1, kRecFinal = 2, kRecInline = 4, kRecGap = 8;
+constexpr uint32_t kRecLive = 1, kRecFinal = 2, kRecInline = 4, kRecGap = 8, kRecGapFin = 16;
 // A gap state (kRecGap) is a state of a bounded any-byte gap: state q with
 // exactly two inline edges, e0 = an edge E and e1 = any byte to q + 1, where
 // q + 1 carries the same E and either continues the gap the same way or
@@ -221,6 +222,9 @@ constexpr uint32_t kRecLive = 1, kRecFinal = 2, kRecInline = 4, kRecGap = 8;
 // (at least 1).  A walk whose whole set is one gap state can pass every byte
 // that E rejects, up to that many, without reading records: each such byte
 // moves it to the next state of the gap.
+// kRecGapFin marks a gap state whose E leads into a simple chain (one edge
+// per state, the last state alone final and without edges).  Its lab_off
+// holds the test of the chain's first edge (0 when E's target is the end).
 
 // The lists of a byte pair in the pair cache: p_st[st_lo, st_hi) and
 // p_lab[lab_lo, lab_hi); one 16-byte load.

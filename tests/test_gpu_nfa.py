@@ -80,6 +80,29 @@ def test_ragged_sizes(P, n):
     check(P, wl.automaton, wl.data[:n])
 
 
+def gap_union(gap_max):
+    """Signature chains with one any-byte gap each: chains of one, two and
+    three states after the gap's exit edge E, and byte classes on E and on
+    the chain's first edge."""
+    S = W.Signature
+    sigs = [S([[97], [98]], 1, 0),                          # a .{0,g} b
+            S([[97], [98], [99]], 1, 1),                    # a .{0,g} b c
+            S([[99], [97, 98], [98], [97], [99]], 2, 2),    # c [ab] .{0,g} b a c
+            S([[100], [97, 98, 99], [97, 99]], 1, 3)]       # d .{0,g} [abc] [ac]
+    return W.union_nfa(sigs, gap_max=gap_max)
+
+
+@pytest.mark.parametrize("gap_max", [8, 64, 100])
+@pytest.mark.parametrize("n", [777, 5000])
+def test_gap_chains(P, gap_max, n):
+    """Gap walks finished in one pass: many exits per gap, walks cut off by
+    the end of the input, gaps longer than one pass covers."""
+    rng = np.random.default_rng(gap_max * 7 + n)
+    x = bytes(rng.choice(list(b"abcd"), n, p=[0.4, 0.3, 0.2, 0.1]).astype(np.uint8))
+    ref = check(P, gap_union(gap_max), x)
+    assert len(ref) > 0
+
+
 def test_cfg3_small(P):
     wl = W.cfg3(seed=33, n=1 << 20, n_patterns=300, plant_rate=5e-4)
     ref = check(P, wl.automaton, wl.data)
