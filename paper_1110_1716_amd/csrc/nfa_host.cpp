@@ -447,8 +447,11 @@ int compute_comp(NfaHost *h, int32_t ci, bool place) {
         // Gap states whose E leads into a simple chain: from E's target on,
         // every state passes exactly one edge to a plain state (its epsilon
         // closure is itself) and is not final, up to a last state with no
-        // edge, which is final.  The attempts E starts at different bytes
-        // then never share a state, and each reports only at the chain's end.
+        // edge, which is final, and every state after the first has only
+        // its predecessor's edge coming in.  The attempts E starts at
+        // different bytes then never share a state, chains after different
+        // first states never meet, and each attempt reports only at its
+        // chain's end.
         // Such a record (never final itself) keeps the chain's first edge
         // test in lab_off.
         for (int32_t i = 0; i < n; ++i) {
@@ -468,6 +471,7 @@ int compute_comp(NfaHost *h, int32_t ci, bool place) {
                     break;
                 }
                 if (fin || u.n_edges != 1 || (u.e0_tgt & kTgtList)) break;
+                if (len > 0 && rev[j].size() != 1) break;  // another way in: chains could merge
                 if (len == 0) t0 = u.e0_test;
                 q = (int32_t)(u.e0_tgt & kStateMask);
             }

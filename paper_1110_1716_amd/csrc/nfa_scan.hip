@@ -51,12 +51,12 @@ struct Big {
     int32_t start, k0, pos0, pad;
 };
 
-// A walk whose whole set is one gap state marked kRecGapFin, waiting for a
-// gap pass (next symbol at pos, k matches reported so far; at most 64
-// any-byte steps left).
+// A walk waiting for a gap pass: its set is n gap states marked kRecGapFin
+// (each with at most 64 any-byte steps left, their chains distinct); next
+// symbol at pos, k matches reported so far.
 struct GapEnt {
-    int32_t start, pos, k;
-    uint32_t g;
+    int32_t start, pos, k, n;
+    uint32_t s[K];
 };
 constexpr int GC = kNfaGapCap;
 
@@ -529,25 +529,27 @@ __device__ __forceinline__ void emit_state(Ctx &c, uint32_t w, int32_t start, in
 }
 
 // Gap pass: up to 64 waiting gap walks, one per lane, each finished at once.
-// From a lone gap state g with r any-byte steps left at position pos, the
+// From a gap state g with r any-byte steps left at position pos, the
 // instance holds the next gap state after each of the symbols pos .. pos +
 // r - 1, and each symbol p in [pos, pos + r] that E accepts starts an
 // attempt along the chain after E.  Attempts started at different symbols
-// are at different chain states at any time (the chain is simple), so the
-// set sizes add up: X gains the gap states plus every attempt's length, the
-// instance lives until the latest of them ends (T counts up to the symbol
-// after it), and attempts that reach the chain's final end report, in order
-// of their first symbol (which is also the order of their ends).  The
-// bytes of [pos, pos + 80] come from six 16-byte loads issued together; E
-// and the chain's first edge are tested on all of them, and only attempts
-// that pass both read on.
+// are at different chain states at any time, and the chains of different
+// gaps never meet, so the set sizes add up: X gains the gap states plus
+// every attempt's length, the instance lives until the latest of them ends
+// (T counts up to the symbol after it), and attempts that reach a chain's
+// final end report, in order of their first symbol (which is also the order
+// of their ends).  The bytes of [pos, pos + 80] come from six 16-byte loads
+// issued together; E and the chain's first edge are tested on all of them,
+// and only attempts that pass both read on.  Reports of two or more gaps
+// would interleave: such a walk is replayed by the workgroup instead.
 template <class Ctx>
-__device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount) {
+__device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount, Big *big_s, int *nbig) {
     const NfaArgs &a = c.a;
     const int lane = lane_id();
     const int take = gcount < 64 ? gcount : 64;
     const bool act = lane < take;
-    GapEnt g{0, 0, 0, 0u};
+    GapEnt g;
+    g.n = 0;
     if (act) g = gl[lane];
     __builtin_amdgcn_wave_barrier();
     for (int e = 64 + lane; e < gcount; e += 64) gl[e - 64] = gl[e];
@@ -556,98 +558,135 @@ __device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount) {
     if (!act) return;
     const int32_t n = c.n32, pos = g.pos;
     const int32_t base = pos & ~15;
-    const NfaRec gr = a.rec[g.g & kStateMask];
-    uint4 G0, G1, G2, G3, G4, G5;
-    {
-        const uint4 z = make_uint4(0, 0, 0, 0);
-        G0 = base < c.nP ? load_granule(c.xa, base) : z;
-        G1 = base + 16 < c.nP ? load_granule(c.xa, base + 16) : z;
-        G2 = base + 32 < c.nP ? load_granule(c.xa, base + 32) : z;
-        G3 = base + 48 < c.nP ? load_granule(c.xa, base + 48) : z;
-        G4 = base + 64 < c.nP ? load_granule(c.xa, base + 64) : z;
-        G5 = base + 80 < c.nP ? load_granule(c.xa, base + 80) : z;
-        c.L += 6;
-    }
-    const int32_t rr = gr.edge_off;  // any-byte steps left, at least 1
-    const uint32_t u0 = gr.e0_tgt;
-    const bool end0 = (u0 & kTgtFinal) != 0;  // E's target ends the chain
-    const ByteTest tE = byte_test(a, gr.e0_test);
-    const ByteTest tT = byte_test(a, end0 ? (1u << 8) : (uint32_t)gr.lab_off);
-    // hE: E accepts the byte at offset o from base; hT: the chain's first
-    // edge accepts it.  The granules move down one register per chunk.
-    unsigned long long hE0 = 0, hE1 = 0, hT0 = 0, hT1 = 0;
-#pragma unroll 1
-    for (int t = 0; t < 6; ++t) {
-        const uint4 v = G0;
-        G0 = G1;
-        G1 = G2;
-        G2 = G3;
-        G3 = G4;
-        G4 = G5;
-        uint32_t e16 = 0, t16 = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int b = byte_of(v, k);
-            e16 |= test_byte(tE, b) << k;
-            t16 |= test_byte(tT, b) << k;
-        }
-        const int sh = 16 * (t & 3);
-        if (t < 4) {
-            hE0 |= (unsigned long long)e16 << sh;
-            hT0 |= (unsigned long long)t16 << sh;
-        } else {
-            hE1 |= (unsigned long long)e16 << sh;
-            hT1 |= (unsigned long long)t16 << sh;
-        }
-    }
-    // Attempts start at [pos, pe]; a second chain state needs one more byte.
-    const int32_t pe = pos + rr < n - 1 ? pos + rr : n - 1;
-    unsigned long long w0, w1, v0, v1;
-    range_bits(pos - base, pe - base, w0, w1);
-    range_bits(pos - base, (pe < n - 2 ? pe : n - 2) - base, v0, v1);
-    const unsigned long long s0 = hE0 & w0, s1 = hE1 & w1;  // attempts
-    long long X = (rr < n - pos ? rr : n - pos) + __popcll(s0) + __popcll(s1);
-    int32_t last = (pos + rr - 1 < n - 1 ? pos + rr - 1 : n - 1);  // the last gap state's symbol
-    const int32_t top1 = s1 ? base + 127 - __clzll(s1) : (s0 ? base + 63 - __clzll(s0) : -1);
-    last = top1 > last ? top1 : last;
+    // One iteration per gap state, then one more that reports for the only
+    // gap whose attempts reach their chain's end (if there is one).
+    uint32_t q0 = g.s[0], q1 = g.s[1], q2 = g.s[2], q3 = g.s[3], qm = 0;
+    int nm = 0;
+    long long X = 0;
+    int32_t last = pos - 1;
     int32_t k = g.k;
-    if (end0) {
-        // E's target is the chain's end: every attempt reports at once.
-        for (int h = 0; h < 2; ++h)
-            for (unsigned long long m = h ? s1 : s0; m; m &= m - 1) {
-                const int32_t p = base + 64 * h + (__ffsll((long long)m) - 1);
-                emit_state(c, u0, g.start, p, k);
-            }
-    } else {
-        // Attempts whose second state is entered (the byte after the first
-        // passes the chain's first edge).
-        const unsigned long long d0 = s0 & v0 & ((hT0 >> 1) | (hT1 << 63)), d1 = s1 & v1 & (hT1 >> 1);
-        X += __popcll(d0) + __popcll(d1);
-        if (d0 | d1) {
-            const uint32_t u1 = a.rec[u0 & kStateMask].e0_tgt;
-            for (int h = 0; h < 2; ++h)
-                for (unsigned long long m = h ? d1 : d0; m; m &= m - 1) {
-                    const int32_t p = base + 64 * h + (__ffsll((long long)m) - 1);
-                    // The attempt holds u at symbol t; it ends at the
-                    // chain's final end or when a byte fails (or the input
-                    // ends).
-                    uint32_t u = u1;
-                    int32_t t = p + 1;
-                    for (;;) {
-                        if (u & kTgtFinal) {
-                            emit_state(c, u, g.start, t, k);
-                            break;
-                        }
-                        if (t + 1 >= n) break;
-                        const NfaRec ru = a.rec[u & kStateMask];
-                        if (!edge_matches(a, ru.e0_test, c.xa[t + 1])) break;
-                        ++X;
-                        u = ru.e0_tgt;
-                        ++t;
-                    }
-                    last = t > last ? t : last;
-                }
+#pragma unroll 1
+    for (int it = 0; it <= g.n; ++it) {
+        const bool em = it == g.n;
+        uint32_t w;
+        if (em) {
+            if (nm != 1) break;
+            w = qm;
+        } else {
+            w = q0;
+            q0 = q1;
+            q1 = q2;
+            q2 = q3;
         }
+        const NfaRec gr = a.rec[w & kStateMask];
+        uint4 G0, G1, G2, G3, G4, G5;  // loaded with the record (again per gap: usually one)
+        {
+            const uint4 z = make_uint4(0, 0, 0, 0);
+            G0 = base < c.nP ? load_granule(c.xa, base) : z;
+            G1 = base + 16 < c.nP ? load_granule(c.xa, base + 16) : z;
+            G2 = base + 32 < c.nP ? load_granule(c.xa, base + 32) : z;
+            G3 = base + 48 < c.nP ? load_granule(c.xa, base + 48) : z;
+            G4 = base + 64 < c.nP ? load_granule(c.xa, base + 64) : z;
+            G5 = base + 80 < c.nP ? load_granule(c.xa, base + 80) : z;
+            c.L += 6;
+        }
+        const int32_t rr = gr.edge_off;  // any-byte steps left, at least 1
+        const uint32_t u0 = gr.e0_tgt;
+        const bool end0 = (u0 & kTgtFinal) != 0;  // E's target ends the chain
+        const ByteTest tE = byte_test(a, gr.e0_test);
+        const ByteTest tT = byte_test(a, end0 ? (1u << 8) : (uint32_t)gr.lab_off);
+        // hE: E accepts the byte at offset o from base; hT: the chain's first
+        // edge accepts it.  The granules move down one register per chunk.
+        unsigned long long hE0 = 0, hE1 = 0, hT0 = 0, hT1 = 0;
+#pragma unroll 1
+        for (int t = 0; t < 6; ++t) {
+            const uint4 v = G0;
+            G0 = G1;
+            G1 = G2;
+            G2 = G3;
+            G3 = G4;
+            G4 = G5;
+            uint32_t e16 = 0, t16 = 0;
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int b = byte_of(v, kk);
+                e16 |= test_byte(tE, b) << kk;
+                t16 |= test_byte(tT, b) << kk;
+            }
+            const int sh = 16 * (t & 3);
+            if (t < 4) {
+                hE0 |= (unsigned long long)e16 << sh;
+                hT0 |= (unsigned long long)t16 << sh;
+            } else {
+                hE1 |= (unsigned long long)e16 << sh;
+                hT1 |= (unsigned long long)t16 << sh;
+            }
+        }
+        // Attempts start at [pos, pe]; a second chain state needs one more byte.
+        const int32_t pe = pos + rr < n - 1 ? pos + rr : n - 1;
+        unsigned long long w0, w1, v0, v1;
+        range_bits(pos - base, pe - base, w0, w1);
+        range_bits(pos - base, (pe < n - 2 ? pe : n - 2) - base, v0, v1);
+        const unsigned long long s0 = hE0 & w0, s1 = hE1 & w1;  // attempts
+        long long Xc = (rr < n - pos ? rr : n - pos) + __popcll(s0) + __popcll(s1);
+        int32_t lc = (pos + rr - 1 < n - 1 ? pos + rr - 1 : n - 1);  // the last gap state's symbol
+        const int32_t top1 = s1 ? base + 127 - __clzll(s1) : (s0 ? base + 63 - __clzll(s0) : -1);
+        lc = top1 > lc ? top1 : lc;
+        bool hit = false;
+        if (end0) {
+            // E's target is the chain's end: every attempt reports at once.
+            hit = (s0 | s1) != 0;
+            if (em)
+                for (int h = 0; h < 2; ++h)
+                    for (unsigned long long m = h ? s1 : s0; m; m &= m - 1)
+                        emit_state(c, u0, g.start, base + 64 * h + (__ffsll((long long)m) - 1), k);
+        } else {
+            // Attempts whose second state is entered (the byte after the
+            // first passes the chain's first edge).
+            const unsigned long long d0 = s0 & v0 & ((hT0 >> 1) | (hT1 << 63)), d1 = s1 & v1 & (hT1 >> 1);
+            Xc += __popcll(d0) + __popcll(d1);
+            if (d0 | d1) {
+                const uint32_t u1 = a.rec[u0 & kStateMask].e0_tgt;
+                for (int h = 0; h < 2; ++h)
+                    for (unsigned long long m = h ? d1 : d0; m; m &= m - 1) {
+                        const int32_t p = base + 64 * h + (__ffsll((long long)m) - 1);
+                        // The attempt holds u at symbol t; it ends at the
+                        // chain's final end or when a byte fails (or the
+                        // input ends).
+                        uint32_t u = u1;
+                        int32_t t = p + 1;
+                        for (;;) {
+                            if (u & kTgtFinal) {
+                                hit = true;
+                                if (em) emit_state(c, u, g.start, t, k);
+                                break;
+                            }
+                            if (t + 1 >= n) break;
+                            const NfaRec ru = a.rec[u & kStateMask];
+                            if (!edge_matches(a, ru.e0_test, c.xa[t + 1])) break;
+                            ++Xc;
+                            u = ru.e0_tgt;
+                            ++t;
+                        }
+                        lc = t > lc ? t : lc;
+                    }
+            }
+        }
+        if (!em) {
+            X += Xc;
+            last = lc > last ? lc : last;
+            if (hit) {
+                ++nm;
+                qm = w;
+            }
+        }
+    }
+    if (nm >= 2) {
+        // Replayed by the workgroup from its start: T and X from pos on,
+        // reports from the k-th on.
+        const int slot = atomicAdd(nbig, 1);
+        if (slot < BC) big_s[slot] = Big{g.start, g.k, pos, 0};
+        return;
     }
     c.X += X;
     c.T += (last - pos + 2 < n - pos ? last - pos + 2 : n - pos);
@@ -699,14 +738,29 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
             for (int t = 0; t < K; ++t)
                 if (act[j] && t < e[j].n) r[j][t] = a.rec[e[j].s[t] & kStateMask];
         if constexpr (!Ctx::kCarryOn) {
-            // A lone gap state whose gap ends in a simple chain waits for a
-            // gap pass instead, once at most 64 any-byte steps remain.
+            // A set of gap states whose gaps end in simple chains (once at
+            // most 64 any-byte steps remain in each), the chains distinct,
+            // waits for a gap pass instead.
 #pragma unroll
             for (int j = 0; j < QK; ++j) {
-                const bool fin = act[j] && e[j].n == 1 && (r[j][0].info & kRecGapFin) && r[j][0].edge_off <= 64;
+                bool fin = act[j];
+#pragma unroll
+                for (int t = 0; t < K; ++t)
+                    if (t < e[j].n) fin = fin && (r[j][t].info & kRecGapFin) && r[j][t].edge_off <= 64;
+#pragma unroll
+                for (int t = 1; t < K; ++t)
+#pragma unroll
+                    for (int t2 = 0; t2 < t; ++t2)
+                        if (t < e[j].n) fin = fin && ((r[j][t].e0_tgt ^ r[j][t2].e0_tgt) & kStateMask) != 0;
                 const int slot = wave_push_slot(gcount, fin);
                 if (fin) {
-                    gl[slot] = GapEnt{e[j].start, e[j].pos, e[j].k, e[j].s[0]};
+                    GapEnt *ge = gl + slot;
+                    ge->start = e[j].start;
+                    ge->pos = e[j].pos;
+                    ge->k = e[j].k;
+                    ge->n = e[j].n;
+#pragma unroll
+                    for (int t = 0; t < K; ++t) ge->s[t] = e[j].s[t];
                     act[j] = false;
                     alive[j] = false;
                 }
@@ -764,7 +818,7 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
     qcount = nc;
     // A round adds at most QW gap walks, so fewer than 64 must wait after it.
     if constexpr (!Ctx::kCarryOn)
-        while (gcount >= 64) gap_pass(c, gl, gcount);
+        while (gcount >= 64) gap_pass(c, gl, gcount, big_s, nbig);
 }
 
 template <bool kCarry>
@@ -981,7 +1035,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         }
         while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
         if constexpr (!kCarry)
-            while (gcount > 0) gap_pass(c, gl, gcount);
+            while (gcount > 0) gap_pass(c, gl, gcount, big_s, &nbig);
         __syncthreads();
         if (nbig > BC) {
             // more starts overflowed than the list holds: the whole segment
