@@ -913,7 +913,8 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         __syncthreads();
     };
     // Replay the listed starts once the list is half full (a uniform
-    // decision taken at the end of each window).
+    // decision taken at the end of every fourth window: each check holds
+    // the workgroup's waves until the slowest arrives).
     auto replay_if_full = [&](int &qcount) __attribute__((always_inline)) {
         __syncthreads();
         const int pending = nbig;
@@ -1031,7 +1032,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-            replay_if_full(qcount);
+            if ((((wbase - (own_lo & ~(int64_t)15)) / W) & 3) == 3) replay_if_full(qcount);
         }
         while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
         if constexpr (!kCarry)
