@@ -914,7 +914,8 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     };
     // Replay the listed starts once the list is half full (a uniform
     // decision taken at the end of every fourth window: each check holds
-    // the workgroup's waves until the slowest arrives).
+    // the workgroup's waves until the slowest arrives).  Returns the number
+    // of listed starts seen.
     auto replay_if_full = [&](int &qcount) __attribute__((always_inline)) {
         __syncthreads();
         const int pending = nbig;
@@ -923,6 +924,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
             while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
             run_big();
         }
+        return pending;
     };
 
     for (;;) {
@@ -944,6 +946,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
         c.seg_lo = own_lo;
         const long long m_before = c.M, t_before = c.T, x_before = c.X;
         int qcount = 0;
+        bool checking = true;
         for (int64_t wbase = own_lo & ~(int64_t)15; wbase < own_hi; wbase += W) {
             const int64_t i0 = wbase + 16 * tid;
             const uint4 mine = i0 < c.nP ? load_granule(c.xa, i0) : make_uint4(0, 0, 0, 0);
@@ -1032,7 +1035,10 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-            if ((((wbase - (own_lo & ~(int64_t)15)) / W) & 3) == 3) replay_if_full(qcount);
+            // The segment's end replays anyway; a segment whose list stays
+            // short by its first check stops checking.
+            if ((((wbase - (own_lo & ~(int64_t)15)) / W) & 3) == 3 && wbase + W < own_hi && checking)
+                checking = replay_if_full(qcount) > BC / 8;
         }
         while (qcount > 0) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
         if constexpr (!kCarry)
