@@ -59,6 +59,9 @@ struct GapEnt {
     uint32_t s[K];
 };
 constexpr int GC = kNfaGapCap;
+// A round adds at most QW walks to fewer than 64 waiting; during a pass at
+// most QW - 1 wait, so the last 64 entries hold a 32-byte bitmap per lane.
+static_assert(sizeof(GapEnt) >= 32 && GC >= 64 + QW, "gap list too small");
 
 // Where a walk's matches go.
 enum Mode : int { kBuffer = 0, kCount = 1, kWrite = 2 };
@@ -487,20 +490,70 @@ __device__ __forceinline__ long long walk_block(Ctx &c, int32_t s, int32_t k0, i
 // the workgroup's replay list.  A lane's walks advance together, one symbol
 // each per step, and the state records of all of them are requested before
 // any is used, so their L2 round trips overlap.
-// An edge test prepared for many bytes: a byte, any byte, or a class
-// bitmap read through the cache.
-struct ByteTest {
-    uint32_t kind, val;
-    const uint32_t *cls;
-};
-__device__ __forceinline__ ByteTest byte_test(const NfaArgs &a, uint32_t test) {
+// Which of 16 bytes an edge test accepts (bit k for byte k of v).  A
+// single byte is compared four at a time (a byte of w ^ the repeated byte is
+// zero exactly when 0x80 ends up set in it); a class reads its bitmap from
+// bm, a 32-byte copy in LDS.
+__device__ __forceinline__ uint32_t test16(uint32_t test, const uint8_t *bm, uint4 v) {
     const uint32_t kind = (test >> 8) & 3u;
-    return ByteTest{kind, test & 255u, kind == 2 ? a.class_bits + (size_t)(test >> 10) * 8 : nullptr};
+    if (kind == 1) return 0xffffu;
+    uint32_t r = 0;
+    if (kind == 0) {
+        const uint32_t rep = (test & 255u) * 0x01010101u;
+        const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t w = q[i] ^ rep;
+            const uint32_t z = ~(((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w | 0x7f7f7f7fu);
+            r |= (((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) | ((z >> 28) & 8u)) << (4 * i);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int b = byte_of(v, k);
+            r |= ((uint32_t)(bm[b >> 3] >> (b & 7)) & 1u) << k;
+        }
+    }
+    return r;
 }
-__device__ __forceinline__ uint32_t test_byte(const ByteTest &t, int b) {
-    if (t.kind == 0) return (uint32_t)b == t.val ? 1u : 0u;
-    if (t.kind == 1) return 1u;
-    return (t.cls[b >> 5] >> (b & 31)) & 1u;
+
+// The bytes [base, base + 96) that an edge test accepts, as a 96-bit mask
+// (h0: offsets 0-63, h1: 64-95).  A class bitmap is first copied to bm.
+template <class Ctx>
+__device__ __forceinline__ void mask96(Ctx &c, uint32_t test, uint8_t *bm, int32_t base, unsigned long long &h0,
+                                       unsigned long long &h1) {
+    if (((test >> 8) & 3u) == 2) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(c.a.class_bits + (size_t)(test >> 10) * 8);
+        const uint4 b0 = p[0], b1 = p[1];
+        reinterpret_cast<uint4 *>(bm)[0] = b0;
+        reinterpret_cast<uint4 *>(bm)[1] = b1;
+    }
+    uint4 G0, G1, G2, G3, G4, G5;
+    {
+        const uint4 z = make_uint4(0, 0, 0, 0);
+        G0 = base < c.nP ? load_granule(c.xa, base) : z;
+        G1 = base + 16 < c.nP ? load_granule(c.xa, base + 16) : z;
+        G2 = base + 32 < c.nP ? load_granule(c.xa, base + 32) : z;
+        G3 = base + 48 < c.nP ? load_granule(c.xa, base + 48) : z;
+        G4 = base + 64 < c.nP ? load_granule(c.xa, base + 64) : z;
+        G5 = base + 80 < c.nP ? load_granule(c.xa, base + 80) : z;
+        c.L += 6;
+    }
+    h0 = 0;
+    h1 = 0;
+    // The granules move down one register per chunk.
+#pragma unroll 1
+    for (int t = 0; t < 6; ++t) {
+        const uint4 v = G0;
+        G0 = G1;
+        G1 = G2;
+        G2 = G3;
+        G3 = G4;
+        G4 = G5;
+        const unsigned long long m = test16(test, bm, v);
+        if (t < 4) h0 |= m << (16 * t);
+        else h1 |= m << (16 * (t - 4));
+    }
 }
 
 // Bits [lo, hi] of a 128-bit mask (h0: bits 0-63, h1: 64-127); empty when
@@ -539,8 +592,8 @@ __device__ __forceinline__ void emit_state(Ctx &c, uint32_t w, int32_t start, in
 // (T counts up to the symbol after it), and attempts that reach a chain's
 // final end report, in order of their first symbol (which is also the order
 // of their ends).  The bytes of [pos, pos + 80] come from six 16-byte loads
-// issued together; E and the chain's first edge are tested on all of them,
-// and only attempts that pass both read on.  Reports of two or more gaps
+// issued together; E is tested on all of them, the chain's first edge too
+// when E accepts some, and only attempts that pass both read on.  Reports of two or more gaps
 // would interleave: such a walk is replayed by the workgroup instead.
 template <class Ctx>
 __device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount, Big *big_s, int *nbig) {
@@ -558,6 +611,9 @@ __device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount, Big *b
     if (!act) return;
     const int32_t n = c.n32, pos = g.pos;
     const int32_t base = pos & ~15;
+    // The list's last 64 entries are free during a pass (fewer than 128
+    // wait): one 32-byte slot per lane holds a class bitmap.
+    uint8_t *bm = reinterpret_cast<uint8_t *>(gl + GC - 64 + lane);
     // One iteration per gap state, then one more that reports for the only
     // gap whose attempts reach their chain's end (if there is one).
     uint32_t q0 = g.s[0], q1 = g.s[1], q2 = g.s[2], q3 = g.s[3], qm = 0;
@@ -579,49 +635,12 @@ __device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount, Big *b
             q2 = q3;
         }
         const NfaRec gr = a.rec[w & kStateMask];
-        uint4 G0, G1, G2, G3, G4, G5;  // loaded with the record (again per gap: usually one)
-        {
-            const uint4 z = make_uint4(0, 0, 0, 0);
-            G0 = base < c.nP ? load_granule(c.xa, base) : z;
-            G1 = base + 16 < c.nP ? load_granule(c.xa, base + 16) : z;
-            G2 = base + 32 < c.nP ? load_granule(c.xa, base + 32) : z;
-            G3 = base + 48 < c.nP ? load_granule(c.xa, base + 48) : z;
-            G4 = base + 64 < c.nP ? load_granule(c.xa, base + 64) : z;
-            G5 = base + 80 < c.nP ? load_granule(c.xa, base + 80) : z;
-            c.L += 6;
-        }
         const int32_t rr = gr.edge_off;  // any-byte steps left, at least 1
         const uint32_t u0 = gr.e0_tgt;
         const bool end0 = (u0 & kTgtFinal) != 0;  // E's target ends the chain
-        const ByteTest tE = byte_test(a, gr.e0_test);
-        const ByteTest tT = byte_test(a, end0 ? (1u << 8) : (uint32_t)gr.lab_off);
-        // hE: E accepts the byte at offset o from base; hT: the chain's first
-        // edge accepts it.  The granules move down one register per chunk.
-        unsigned long long hE0 = 0, hE1 = 0, hT0 = 0, hT1 = 0;
-#pragma unroll 1
-        for (int t = 0; t < 6; ++t) {
-            const uint4 v = G0;
-            G0 = G1;
-            G1 = G2;
-            G2 = G3;
-            G3 = G4;
-            G4 = G5;
-            uint32_t e16 = 0, t16 = 0;
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const int b = byte_of(v, kk);
-                e16 |= test_byte(tE, b) << kk;
-                t16 |= test_byte(tT, b) << kk;
-            }
-            const int sh = 16 * (t & 3);
-            if (t < 4) {
-                hE0 |= (unsigned long long)e16 << sh;
-                hT0 |= (unsigned long long)t16 << sh;
-            } else {
-                hE1 |= (unsigned long long)e16 << sh;
-                hT1 |= (unsigned long long)t16 << sh;
-            }
-        }
+        // hE: E accepts the byte at offset o from base.
+        unsigned long long hE0, hE1;
+        mask96(c, gr.e0_test, bm, base, hE0, hE1);
         // Attempts start at [pos, pe]; a second chain state needs one more byte.
         const int32_t pe = pos + rr < n - 1 ? pos + rr : n - 1;
         unsigned long long w0, w1, v0, v1;
@@ -640,9 +659,11 @@ __device__ __forceinline__ void gap_pass(Ctx &c, GapEnt *gl, int &gcount, Big *b
                 for (int h = 0; h < 2; ++h)
                     for (unsigned long long m = h ? s1 : s0; m; m &= m - 1)
                         emit_state(c, u0, g.start, base + 64 * h + (__ffsll((long long)m) - 1), k);
-        } else {
+        } else if (s0 | s1) {
             // Attempts whose second state is entered (the byte after the
-            // first passes the chain's first edge).
+            // first passes the chain's first edge, hT).
+            unsigned long long hT0, hT1;
+            mask96(c, (uint32_t)gr.lab_off, bm, base, hT0, hT1);
             const unsigned long long d0 = s0 & v0 & ((hT0 >> 1) | (hT1 << 63)), d1 = s1 & v1 & (hT1 >> 1);
             Xc += __popcll(d0) + __popcll(d1);
             if (d0 | d1) {
