@@ -25,6 +25,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "dfa_defer.h"
 #include "host_common.h"
 #include "pfsm_nfa.h"
 #include "stream.h"
@@ -1079,8 +1080,22 @@ int nfa_launch(NfaHost *h, const uint8_t *x, int64_t n, const SegPlan *plan, int
     // after any growth of the look-back words above
     a.lb = w->lb;
     a.lb_cap = w->lb_cap;
-    void *args[] = {&a};
+    // A plain scan places its segments' matches after the scan (dfa_defer.h).
+    DfaDefer d;
+    std::memset(&d, 0, sizeof d);
+    if (!plan && !carry && !d_base && a.n_segs >= kDeferMinSegs) {
+        const int64_t rows = std::min<int64_t>((int64_t)a.n_segs * kNfaMatchCap, kDeferRowsMax);
+        if ((rc = grow_defer(w, a.n_segs, rows))) return rc;
+        d.stage = w->defer_rows;
+        d.stage_cap = std::min<int64_t>(w->c_defer_rows, cap);
+        d.cursor = w->defer_cursor;
+        d.seg_at = w->defer_seg;
+        d.seg_cnt = w->defer_seg + w->c_defer_seg;
+        d.seg_base = w->defer_seg + 2 * w->c_defer_seg;
+    }
+    void *args[] = {&a, &d};
     HIP_TRY(hipLaunchKernel(nfa_kernel_fn(carry != nullptr), dim3(grid), dim3(kNfaThreads), args, 0, s));
+    if (d.stage) HIP_TRY(launch_dfa_place(d, a.n_segs, d_total, out, cap, s));
     w->last_grid = grid;
     h->pool.mark(w);
     return PFSM_OK;

@@ -27,6 +27,7 @@
 //     from decoupled look-back over the segment tickets as in the DFA scan; a
 //     segment whose matches overflow the buffer is walked again 256 starts at
 //     a time to count, scan and write.
+#include "dfa_defer.h"
 #include "scan_common.h"
 #include "stream.h"
 
@@ -843,7 +844,7 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
 }
 
 template <bool kCarry>
-__global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
+__global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
     __shared__ uint32_t pbits_s[2048];
     __shared__ int32_t f1o_s[257];
     __shared__ int32_t e1o_s[257];
@@ -860,7 +861,8 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
     __shared__ int sh[16];
     __shared__ long long red[NT / 64];
     __shared__ long long red4[4 * (NT / 64)];
-    __shared__ long long ex_s, base_s, segsz_s;
+    __shared__ long long ex_s, base_s, segsz_s, dat_s;
+    __shared__ int defer_s;
     __shared__ unsigned epoch_s;
 
     const int tid = threadIdx.x;
@@ -1096,12 +1098,37 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
             c.M = m_before + seg_m;
         }
 
-        // The segment's count, its offset by look-back, and placement.
+        // The segment's count, then its placement: staged for a follow-up
+        // launch (plain scans, as in the DFA scan), or at the offset found by
+        // look-back.
         const long long mine_m = block_sum<NT>(seg_m, red);
-        if (tid == 0) seg_s = take_ticket(a.ctl);  // the next segment, requested early
-        if (wv == 0) {
+        if (tid == 0) {
+            seg_s = take_ticket(a.ctl);  // the next segment, requested early
+            defer_s = 0;
+            if (d.stage && !ovf) {
+                const long long at = mine_m ? (long long)atomicAdd(d.cursor, (unsigned long long)mine_m) : 0;
+                if (at + mine_m <= d.stage_cap) {
+                    defer_s = 1;
+                    dat_s = at;
+                }
+            }
+        }
+        __syncthreads();
+        const bool defer = defer_s != 0;
+        if (defer) {
+            // Publish the count and go on: the offset comes later.
+            if (tid == 0) {
+                d.seg_at[sg] = dat_s;
+                d.seg_cnt[sg] = mine_m;
+                slot_store(&a.lb[sg], lb_pack(epoch, sg == 0 ? kLbIncl : kLbAgg, mine_m));
+            }
+        } else if (wv == 0) {
             const long long ex = lookback(a.lb, sg, epoch, mine_m);
             if (lane == 0) {
+                if (d.stage) {
+                    d.seg_at[sg] = -1;
+                    d.seg_cnt[sg] = mine_m;
+                }
                 ex_s = ex;
                 const long long at = out_base + ex;
                 if (sg == n_segs - 1) *a.total = at + mine_m;
@@ -1130,9 +1157,9 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a) {
                     rank += (k3.x < mk) + (k3.y < mk) + (k3.z < mk) + (k3.w < mk);
                 }
                 for (; j < m; ++j) rank += mkey[j] < mk;
-                const long long at = at0 + rank;
-                if (at < a.cap) {
-                    MatchOut *p = &a.out[at];
+                const long long at = defer ? dat_s + rank : at0 + rank;
+                if (defer || at < a.cap) {
+                    MatchOut *p = defer ? &d.stage[at] : &a.out[at];
                     p->start = (int32_t)(seg_lo + (mk >> 16));  // stream position
                     p->end = mend[e];
                     p->label = mlab[e];

@@ -19,6 +19,8 @@
 #include <string>
 #include <tuple>
 
+#include "dfa_defer.h"
+
 namespace pfsmk {
 std::string &last_error() {
     static std::string s;
@@ -33,6 +35,7 @@ const void *nfa_kernel_fn(bool) {
     return &k;
 }
 hipError_t launch_nfa_resume(const NfaResumeArgs &, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_dfa_place(const DfaDefer &, int, int64_t *, MatchOut *, int64_t, hipStream_t) { return hipSuccess; }
 }  // namespace pfsmk
 
 using namespace pfsmk;
