@@ -1039,11 +1039,29 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
                                 if (a.pair_on) emit_list(c, kBuffer, a.p_lab, llo, lhi, i, i + 1, km, 0, 0);
                                 else emit_set(c, kBuffer, ent.s, nS, i, i + 1, km, 0, 0);
                                 if (nS > 0 && i + 2 < n32) {
-                                    push = true;
-                                    ent.start = i;
-                                    ent.pos = i + 2;
-                                    ent.k = km;
-                                    ent.n = nS;
+                                    // Symbol three here: most of these walks
+                                    // end at it, and only the others queue.
+                                    uint32_t O[K];
+                                    int nO;
+                                    if (!nfa_step(a, ent.s, nS, c.xa[i + 2], O, nO)) {
+                                        const int slot = atomicAdd(&nbig, 1);
+                                        if (slot < BC) big_s[slot] = Big{i, km, i + 2, 0};
+                                    } else {
+                                        ++c.T;
+                                        c.X += nO;
+                                        emit_set(c, kBuffer, O, nO, i, i + 2, km, 0, 0);
+                                        if (nO > 0 && i + 3 < n32) {
+                                            push = true;
+                                            ent.start = i;
+                                            ent.pos = i + 3;
+                                            ent.k = km;
+                                            ent.n = nO;
+#pragma unroll
+                                            for (int t = 0; t < K; ++t) ent.s[t] = O[t];
+                                        } else if (nO > 0) {
+                                            c.carry_set(i, O, nO);
+                                        }
+                                    }
                                 } else if (nS > 0) {
                                     c.carry_set(i, ent.s, nS);
                                 }
