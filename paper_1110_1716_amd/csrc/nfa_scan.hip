@@ -60,6 +60,7 @@ struct GapEnt {
     uint32_t s[K];
 };
 constexpr int GC = kNfaGapCap;
+constexpr int LC = 64 + 8 * 64;  // list: fewer than 64 left over plus one half-window of starts
 // A round adds at most QW walks to fewer than 64 waiting; during a pass at
 // most QW - 1 wait, so the last 64 entries hold a 32-byte bitmap per lane.
 static_assert(sizeof(GapEnt) >= 32 && GC >= 64 + QW, "gap list too small");
@@ -844,13 +845,13 @@ __device__ __forceinline__ void drain_round(Ctx &c, Walk *q, int &qcount, Big *b
 }
 
 template <bool kCarry>
-__global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
+__global__ __launch_bounds__(NT, 2) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
     __shared__ uint32_t pbits_s[2048];
     __shared__ int32_t f1o_s[257];
     __shared__ int32_t e1o_s[257];
     __shared__ int16_t n1_s[256];   // states after the first symbol, by byte
     __shared__ int16_t e1n_s[256];  // labels reported after the first symbol, by byte
-    __shared__ uint32_t lst_all[(NT / 64) * 512];
+    __shared__ uint32_t lst_all[(NT / 64) * LC];
     __shared__ Walk qall[(NT / 64) * QW];
     __shared__ uint32_t mkey[MC];
     __shared__ int32_t mend[MC];
@@ -913,7 +914,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
     NfaCtx<kCarry> c{a, pbits_s, f1o_s, e1o_s, mkey, mend, mlab, &mn, &ovf};
     constexpr bool cy = kCarry;
     Walk *q = qall + wv * QW;
-    uint32_t *lst = lst_all + wv * 512;
+    uint32_t *lst = lst_all + wv * LC;
     GapEnt *gl = kCarry ? gap_all : gap_all + wv * GC;
     int gcount = 0;
 
@@ -969,6 +970,7 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
         c.seg_lo = own_lo;
         const long long m_before = c.M, t_before = c.T, x_before = c.X;
         int qcount = 0;
+        int lcount = 0;  // entries in the wave's list
         bool checking = true;
         for (int64_t wbase = own_lo & ~(int64_t)15; wbase < own_hi; wbase += W) {
             const int64_t i0 = wbase + 16 * tid;
@@ -981,8 +983,10 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
             const int tail = ((vmask >> 15) & 1u) && i0 + 16 < c.nP ? c.xa[i0 + 16] : 0;
             // Every start takes its first symbol (and, when the byte pair has
             // neither states nor labels after two symbols, its second) in
-            // registers; the others are compacted into the wave's list and
-            // taken 64 at a time.
+            // registers; the others are appended to the wave's list, which
+            // is taken 64 entries at a time as it fills (the rest at the
+            // segment's last window), so that every batch of dependent loads
+            // serves a full wave.
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 unsigned lm = 0;
@@ -1006,24 +1010,28 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
                     c.X += valid ? n1 : 0;
                     c.T += (second && !take) ? 1 : 0;
                     lm |= (take ? 1u : 0u) << k8;
-                    ent8[k8] = (uint32_t)(16 * tid + k) | ((uint32_t)c1 << 12) | ((uint32_t)c2 << 20);
+                    ent8[k8] = (uint32_t)(i - own_lo) | ((uint32_t)c1 << 16) | ((uint32_t)c2 << 24);
                 }
                 const int cnt = __popc(lm);
                 int total;
                 const int ex = wave_excl_small(cnt, total);
 #pragma unroll
                 for (int k8 = 0; k8 < 8; ++k8)
-                    if ((lm >> k8) & 1u) lst[ex + __popc(lm & ((1u << k8) - 1u))] = ent8[k8];
+                    if ((lm >> k8) & 1u) lst[lcount + ex + __popc(lm & ((1u << k8) - 1u))] = ent8[k8];
+                lcount += total;
                 __builtin_amdgcn_wave_barrier();
-                for (int e0 = 0; e0 < total; e0 += 64) {
-                    const int e = e0 + lane;
+                const bool last = h == 1 && wbase + W >= own_hi;
+                for (;;) {
+                    const int nb = lcount >= 64 ? 64 : (last ? lcount : 0);
+                    if (nb == 0) break;
+                    const int e = lane;
                     bool push = false;
                     Walk ent;
                     ent.n = 0;
-                    if (e < total) {
+                    if (e < nb) {
                         const uint32_t w = lst[e];
-                        const int32_t i = (int32_t)(wbase + (w & 4095u));
-                        const int c1 = (int)((w >> 12) & 255u), c2 = (int)(w >> 20);
+                        const int32_t i = (int32_t)(own_lo + (w & 0xffffu));
+                        const int c1 = (int)((w >> 16) & 255u), c2 = (int)(w >> 24);
                         int32_t km = 0;
                         emit_list(c, kBuffer, a.e1, e1o_s[c1], e1o_s[c1 + 1], i, i, km, 0, 0);
                         if (i + 1 < n32) {
@@ -1073,8 +1081,12 @@ __global__ __launch_bounds__(NT) void nfa_scan_kernel(NfaArgs a, DfaDefer d) {
                     while (qcount > QW - 64) drain_round(c, q, qcount, big_s, &nbig, gl, gcount);
                     const int slot = wave_push_slot(qcount, push);
                     if (push) q[slot] = ent;
+                    // the batch leaves the list
+                    __builtin_amdgcn_wave_barrier();
+                    for (int m = nb + lane; m < lcount; m += 64) lst[m - nb] = lst[m];
+                    __builtin_amdgcn_wave_barrier();
+                    lcount -= nb;
                 }
-                __builtin_amdgcn_wave_barrier();
             }
             // The segment's end replays anyway; a segment whose list stays
             // short by its first check stops checking.
