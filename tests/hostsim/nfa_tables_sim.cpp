@@ -141,7 +141,62 @@ struct Tables {
     }
 };
 
+// Records marked kRecGapFin (a gap whose walks the scan finishes in one
+// pass) must head a simple chain: from E's target on, every state passes one
+// edge to a plain state and is not final, up to a final state without
+// edges; lab_off holds the chain's first edge test; and no state after the
+// first has another way in.  Returns how many such records there are.
+int check_gap_chains(const NfaHost *h) {
+    const int64_t ns = (int64_t)h->rec.host.size();
+    auto rec = [&](uint32_t w) -> const NfaRec & { return Tables::at(h->rec, (int64_t)(w & kStateMask), "gap chain state"); };
+    std::vector<int32_t> indeg(ns, 0);
+    auto add_tgt = [&](uint32_t w) {
+        if (w & kTgtList) {
+            const int64_t l = (int64_t)(w & ~kTgtList);
+            const int32_t lo = Tables::at(h->cl_off, l, "closure offsets"), hi = Tables::at(h->cl_off, l + 1, "closure offsets");
+            for (int32_t j = lo; j < hi; ++j) ++indeg[Tables::at(h->cl, j, "closure lists") & kStateMask];
+        } else {
+            ++indeg[(int64_t)(w & kStateMask) < ns ? w & kStateMask : 0];
+        }
+    };
+    for (int64_t q = 0; q < ns; ++q) {
+        const NfaRec &r = Tables::at(h->rec, q, "records");
+        if (!(r.info & kRecLive)) continue;
+        if (r.info & kRecInline) {
+            if (r.n_edges > 0) add_tgt(r.e0_tgt);
+            if (r.n_edges > 1) add_tgt(r.e1_tgt);
+        } else {
+            for (int32_t e = 0; e < r.n_edges; ++e) add_tgt(Tables::at(h->edges, 2 * (int64_t)(r.edge_off + e) + 1, "edges"));
+        }
+    }
+    int count = 0;
+    for (int64_t q = 0; q < ns; ++q) {
+        const NfaRec &r = Tables::at(h->rec, q, "records");
+        if (!(r.info & kRecGapFin)) continue;
+        ++count;
+        if (!(r.info & kRecGap) || (r.e0_tgt & kTgtList)) die("gap chain: head is not a plain gap state");
+        uint32_t w = r.e0_tgt;
+        for (int64_t len = 0;; ++len) {
+            const NfaRec &u = rec(w);
+            const bool fin = (w & kTgtFinal) != 0;
+            if (fin != ((u.info & kRecFinal) != 0)) die("gap chain: final flag of a target word");
+            if (len > 0 && indeg[w & kStateMask] != 1) die("gap chain: a later state has another way in");
+            if (fin) {
+                if (!(u.info & kRecInline) || u.n_edges != 0) die("gap chain: final state with edges");
+                break;
+            }
+            if (!(u.info & kRecInline) || u.n_edges != 1 || (u.info & kRecGap) || (u.e0_tgt & kTgtList))
+                die("gap chain: not a simple chain state");
+            if (len == 0 && (uint32_t)r.lab_off != u.e0_test) die("gap chain: first edge test");
+            if (len > ns) die("gap chain: cycle");
+            w = u.e0_tgt;
+        }
+    }
+    return count;
+}
+
 void scan(const NfaHost *h, const std::vector<uint8_t> &x, FILE *o) {
+    fprintf(stderr, "gap chains %d\n", check_gap_chains(h));
     Tables t{h};
     std::set<std::tuple<int, int, int>> M;
     const int32_t n = (int32_t)x.size();

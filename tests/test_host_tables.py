@@ -63,9 +63,11 @@ def expected(base, disabled, added, x):
     return sorted(set(map(tuple, allm.tolist())))
 
 
-def run_case(sim, tmp_path, base, ops_gen, x, rng):
+def run_case(sim, tmp_path, base, ops_gen, x, rng, min_gap_chains=0):
     """ops_gen yields ('a', nfa) / ('r', label) / ('k', 0|1); returns the
-    number of steps checked."""
+    number of steps checked.  The simulator also checks, after every step,
+    that each gap the scan finishes in one pass heads a simple chain; at
+    least min_gap_chains of them must have been seen at some step."""
     path, out = tmp_path / "case.txt", tmp_path / "out.txt"
     ops = list(ops_gen)
     with open(path, "w") as f:
@@ -79,6 +81,8 @@ def run_case(sim, tmp_path, base, ops_gen, x, rng):
                 f.write(f"{op[0]} {op[1]}\n")
     r = subprocess.run([sim, str(path), str(out)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
+    seen = [int(l.split()[-1]) for l in r.stderr.splitlines() if l.startswith("gap chains")]
+    assert max(seen, default=0) >= min_gap_chains, seen
     blocks = open(out).read().split("== ")[1:]
     assert len(blocks) == len(ops) + 1
     # replay the edits on the reference side
@@ -213,4 +217,4 @@ def test_signature_union_many_edits(sim, tmp_path):
         else:
             ops.append(("r", present.pop(int(rng.integers(0, len(present))))))
     x = rng.choice(np.frombuffer(b"abcd", np.uint8), 400)
-    assert run_case(sim, tmp_path, base, iter(ops), x, rng) == 41
+    assert run_case(sim, tmp_path, base, iter(ops), x, rng, min_gap_chains=1) == 41
