@@ -54,10 +54,10 @@ struct Req {
     const uint8_t *src = nullptr;  // the request's bytes (bytes.data() or the caller's)
     int64_t n = 0;
     int64_t exact = -1;  // its match count, once a batch has counted it
-    // its matches: allocated without zero-filling, since the copy from the
-    // batch output writes every row (the copy runs on the pool, so the
-    // first touch of the pages is spread over its threads)
-    std::unique_ptr<pfsm_match_t[]> result;
+    // its matches: rows of its batch's pinned output buffer, which it keeps
+    // alive (shared with the batch's other requests) until it is released
+    const pfsm_match_t *result = nullptr;
+    std::shared_ptr<struct OutBuf> hold;
     int64_t n_result = 0;
     int status = PFSM_OK;
     bool done = false;
@@ -156,6 +156,59 @@ struct Buf {
     }
 };
 
+// A pinned buffer that receives one batch's output.  The batch's requests
+// point into it and share it; when the last of them is released it goes
+// back to the pool for a later batch.
+struct OutBuf {
+    void *p = nullptr;
+    int64_t cap = 0;  // bytes
+};
+
+constexpr int64_t kOutMin = 32ll << 20;  // smallest output buffer allocated, bytes
+
+class OutPool {
+  public:
+    ~OutPool() {
+        for (OutBuf *b : all_) {
+            if (b->p) (void)hipHostFree(b->p);
+            delete b;
+        }
+    }
+    // An idle buffer of at least `bytes`, else a new one.
+    int get(int64_t bytes, std::shared_ptr<OutBuf> *out) {
+        OutBuf *b = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            for (size_t i = 0; i < free_.size(); ++i)
+                if (free_[i]->cap >= bytes) {
+                    b = free_[i];
+                    free_[i] = free_.back();
+                    free_.pop_back();
+                    break;
+                }
+        }
+        if (!b) {
+            std::unique_ptr<OutBuf> nb(new (std::nothrow) OutBuf);
+            if (!nb) return fail(PFSM_ENOMEM, "out of host memory");
+            const int64_t n = std::max<int64_t>(bytes, kOutMin);
+            HIP_TRY(hipHostMalloc(&nb->p, (size_t)n, hipHostMallocDefault));
+            nb->cap = n;
+            b = nb.release();
+            std::lock_guard<std::mutex> lk(m_);
+            all_.push_back(b);
+        }
+        *out = std::shared_ptr<OutBuf>(b, [this](OutBuf *x) {
+            std::lock_guard<std::mutex> lk(m_);
+            free_.push_back(x);
+        });
+        return PFSM_OK;
+    }
+
+  private:
+    std::mutex m_;
+    std::vector<OutBuf *> free_, all_;
+};
+
 // Host and device buffers of one batch in flight.
 struct Slot {
     hipStream_t stream = nullptr;
@@ -167,17 +220,15 @@ struct Slot {
     Buf h_data{nullptr, 0, true}, h_off{nullptr, 0, true}, h_aut{nullptr, 0, true}, h_moff{nullptr, 0, true},
         h_info{nullptr, 0, true}, h_lohi{nullptr, 0, true};
     // The batch copies its whole output reservation to the host in stream
-    // order, into one of two pinned buffers: the next batch of the slot uses
-    // the other one while this one's results are copied out to the callers.
-    Buf h_out[2] = {{nullptr, 0, true}, {nullptr, 0, true}};
-    int hk = 0;  // the buffer of the batch in flight
+    // order, into a pinned buffer from the pool that its requests keep.
+    std::shared_ptr<OutBuf> h_out;
     Buf d_data, d_off, d_aut, d_moff, d_out;
     BatchRun run;
 
     void release() {
-        for (Buf *b : {&h_data, &h_off, &h_aut, &h_moff, &h_out[0], &h_out[1], &h_info, &h_lohi, &d_data, &d_off,
-                       &d_aut, &d_moff, &d_out})
+        for (Buf *b : {&h_data, &h_off, &h_aut, &h_moff, &h_info, &h_lohi, &d_data, &d_off, &d_aut, &d_moff, &d_out})
             b->release();
+        h_out.reset();
         if (ev) (void)hipEventDestroy(ev);
         if (stream) (void)hipStreamDestroy(stream);
         ev = nullptr;
@@ -188,6 +239,7 @@ struct Slot {
 }  // namespace
 
 struct pfsm_server {
+    OutPool out_pool;  // first: outlives the requests and slots that share its buffers
     std::vector<pfsm_t *> hs;
     int device = 0;
     int64_t budget = 0;
@@ -266,7 +318,7 @@ struct pfsm_server {
         if ((rc = sl.h_aut.reserve(4 * nr))) return rc;
         if ((rc = sl.d_aut.reserve(4 * nr))) return rc;
         if ((rc = sl.d_out.reserve(sl.out_cap * (int64_t)sizeof(MatchOut)))) return rc;
-        if ((rc = sl.h_out[sl.hk].reserve(std::max<int64_t>(sl.out_cap, 1) * (int64_t)sizeof(MatchOut)))) return rc;
+        if ((rc = out_pool.get(std::max<int64_t>(sl.out_cap, 1) * (int64_t)sizeof(MatchOut), &sl.h_out))) return rc;
         if ((rc = sl.h_info.reserve(sizeof(BatchInfo)))) return rc;
         const int64_t t0 = now_ns();
         int64_t pos = 0;
@@ -292,7 +344,7 @@ struct pfsm_server {
         HIP_TRY(hipMemcpyAsync(sl.h_moff.p, sl.d_moff.p, 8 * (nr + 1), hipMemcpyDeviceToHost, sl.stream));
         HIP_TRY(hipMemcpyAsync(sl.h_info.p, sl.run.info, sizeof(BatchInfo), hipMemcpyDeviceToHost, sl.stream));
         if (sl.out_cap > 0)
-            HIP_TRY(hipMemcpyAsync(sl.h_out[sl.hk].p, sl.d_out.p, sl.out_cap * (int64_t)sizeof(MatchOut),
+            HIP_TRY(hipMemcpyAsync(sl.h_out->p, sl.d_out.p, sl.out_cap * (int64_t)sizeof(MatchOut),
                                    hipMemcpyDeviceToHost, sl.stream));
         HIP_TRY(hipEventRecord(sl.ev, sl.stream));
         std::lock_guard<std::mutex> lk(mu);
@@ -330,11 +382,11 @@ struct pfsm_server {
             for (int64_t j = 0; j < nr; ++j) whole[j] = mo[j + 1] <= sl.out_cap && hi[j] <= sl.run.stage_cap;
         }
         const int64_t t0 = now_ns();
-        // the batch's output rows, min(total, out_cap), are in h_out[hk]
-        const pfsm_match_t *m = sl.h_out[sl.hk].as<pfsm_match_t>();
+        // the batch's output rows, min(total, out_cap), are in h_out: each
+        // whole request's results are its rows there
+        const pfsm_match_t *m = static_cast<const pfsm_match_t *>(sl.h_out->p);
         std::vector<Req *> redo;
         std::vector<Req *> done;
-        std::vector<std::tuple<void *, const void *, int64_t>> parts;
         for (int64_t j = 0; j < nr; ++j) {
             Req *r = sl.reqs[j];
             const int64_t k = mo[j + 1] - mo[j];
@@ -343,14 +395,9 @@ struct pfsm_server {
                 density[r->aut] = std::max(d, 0.8 * density[r->aut] + 0.2 * d);
             }
             if (whole[j]) {
-                r->result.reset(k ? new (std::nothrow) pfsm_match_t[k] : nullptr);
-                if (k && !r->result) {
-                    r->status = PFSM_ENOMEM;
-                    r->n_result = 0;
-                } else {
-                    r->n_result = k;
-                    if (k) parts.emplace_back(r->result.get(), m + mo[j], k * (int64_t)sizeof(pfsm_match_t));
-                }
+                r->result = k ? m + mo[j] : nullptr;
+                if (k) r->hold = sl.h_out;
+                r->n_result = k;
                 done.push_back(r);
             } else {
                 r->exact = k;
@@ -362,22 +409,21 @@ struct pfsm_server {
             for (auto it = redo.rbegin(); it != redo.rend(); ++it) queue.push_front(*it);
             ++st.reruns;
         }
-        // Hand the slot to the next batch before copying these results out:
-        // its inputs and device buffers are free now, and the matches stay
-        // in h_out, which a batch touches only when it completes.
+        // Hand the slot to the next batch: its inputs and device buffers are
+        // free now, and the matches stay in the output buffer the requests
+        // hold.
         const int64_t t1 = now_ns();
         const int64_t bytes = sl.bytes;
         inflight -= charge(bytes, sl.out_cap);
         sl.reqs.clear();
         sl.busy = false;
-        sl.hk ^= 1;  // the results being copied out stay in the other buffer
+        sl.h_out.reset();
         if (admit(sl)) {
             sl.busy = true;
             const int lrc = launch(sl);
             if (lrc) finish(sl, lrc);
         }
         const int64_t t2 = now_ns();
-        copy_all(parts);
         int64_t delivered = 0;
         for (Req *r : done) delivered += r->n_result;
         {
@@ -530,7 +576,7 @@ int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches
     Req *r = it->second.get();
     sv->cv_done.wait(lk, [&] { return r->done; });
     if (r->status != PFSM_OK) return fail(r->status, "request %lld failed", (long long)id);
-    *matches = r->result.get();
+    *matches = r->result;
     *n_matches = r->n_result;
     return PFSM_OK;
 }
