@@ -375,11 +375,12 @@ int pfsm_server_submit(pfsm_server_t *sv, int32_t automaton, const uint8_t *byte
  * request is finished, and the caller keeps them unchanged until then.    */
 int pfsm_server_submit_borrowed(pfsm_server_t *sv, int32_t automaton, const uint8_t *bytes, int64_t n,
                                 int64_t *id);
-/* Block until request `id` is done; *matches (host memory owned by the
- * server until pfsm_server_release; NULL when *n_matches is 0) holds its
- * *n_matches matches in ascending (start, end, label) order.  Errors:
- * PFSM_ENOENT, PFSM_ENOMEM when the host result buffer could not be
- * allocated, or the error the request's batch met.                        */
+/* Block until request `id` is done; *matches (pinned host memory owned by
+ * the server, shared with the other requests of its batch and valid until
+ * pfsm_server_release; NULL when *n_matches is 0) holds its *n_matches
+ * matches in ascending (start, end, label) order.  Errors: PFSM_ENOENT, or
+ * the error the request's batch met (PFSM_ENOMEM or PFSM_EHIP when its
+ * host output buffer could not be allocated).                              */
 int pfsm_server_wait(pfsm_server_t *sv, int64_t id, const pfsm_match_t **matches, int64_t *n_matches);
 /* When request `id` was submitted and finished (results on the host), in
  * CLOCK_MONOTONIC nanoseconds; *t_done_ns is 0 while it is not finished.
