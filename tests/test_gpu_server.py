@@ -161,6 +161,47 @@ def test_wait_then_release_and_empty_results(P):
         h.free()
 
 
+def test_held_results_survive_later_batches(P):
+    # requests of one batch share its pinned result rows: a result held past
+    # the release of its batch-mates and across later batches (which recycle
+    # released result buffers) still reads as the oracle's
+    w3 = W.cfg3(seed=21, n=1 << 16, n_patterns=120, plant_rate=2e-3)
+    autos = [W.cfg1(seed=5).automaton, w3.automaton]
+    hs = [P.pfsm_load(a) for a in autos]
+    rng = np.random.default_rng(12)
+
+    def req(a):
+        n = int(rng.integers(2000, 30000))
+        if a == 0:
+            return (rng.integers(0, 4, n) + ord("a")).astype(np.uint8)
+        o = int(rng.integers(0, w3.data.size - n))
+        return np.ascontiguousarray(w3.data[o:o + n])
+
+    first = [(a, req(a)) for a in (0, 1, 0, 1, 0, 1)]
+    with P.Server(hs, mem_budget=64 << 20, max_batch=8) as sv:
+        ids = [sv.submit(a, x) for a, x in first]
+        reads = [sv.wait(i, release=False) for i in ids]
+        held = ids[::2] + ids[1:2]
+        for i in ids[3::2]:
+            sv.release(i)
+        for _ in range(4):
+            more = [(int(a), req(int(a))) for a in rng.integers(0, 2, 6)]
+            got = [sv.wait(i) for i in [sv.submit(a, x) for a, x in more]]
+            for (a, x), g in zip(more, got):
+                assert np.array_equal(g, oracle.scan(autos[a], x)[0])
+        again = [sv.wait(i, release=False) for i in held]
+        for i in held:
+            sv.release(i)
+    for (a, x), got in zip(first, reads):
+        ref, _ = oracle.scan(autos[a], x)
+        assert len(ref) > 0
+        assert np.array_equal(got, ref)
+    for i, g in zip(held, again):
+        assert np.array_equal(g, reads[ids.index(i)])
+    for h in hs:
+        h.free()
+
+
 def test_cfg5_full_size_alone_equals_mixed(P):
     """The served workload at its stated size: 8 resident automata (4 random
     16-state DFAs, 4 NFA unions of 2,000 signatures) and requests log-uniform
