@@ -327,6 +327,77 @@ __device__ __forceinline__ bool advance_staged(DfaCtx<ENC, kId> &c, bool act, in
     return alive && pos < c.n32;
 }
 
+// advance_staged for the 8-bit resident tables with byte-indexed rows.  The
+// target of the next byte is carried as the stored byte u and a dead bit d
+// (kEnc8: u = 255 marks no transition and its flag entry is zero; kEnc8D: the
+// table's dead bit).  A step reads the flag of u, the table entry and dead
+// word of (u, next byte) and the byte after, together; the walk's running,
+// live and final conditions are kept as 0/1 integers so that a step is
+// straight-line vector code.  The walk's counts come from the distance
+// walked: X = bytes entered, T adds the killing byte of a walk that ends
+// before `lim`.
+template <int ENC>
+__device__ __forceinline__ bool advance_staged8(DfaCtx<ENC, true> &c, bool act, int32_t start, int &s, int32_t &pos,
+                                                int32_t &k, int32_t lim) {
+    static_assert(ENC == kEnc8 || ENC == kEnc8D, "8-bit byte-indexed tables only");
+    const uint8_t *fl = c.flags_s;
+    const uint8_t *tb = c.tab_s;
+    const uint32_t *dead = reinterpret_cast<const uint32_t *>(c.tab_s + 65536);
+    const uint32_t rmax = (uint32_t)c.a.n_states - 1u;
+    const int32_t p0 = pos;
+    // Byte p of the staged pair is rb[p - pos].  Running walks read at most
+    // two bytes past the pair, which stay inside LDS (the next wave's ring or
+    // the fixed head after the last one).
+    const uint8_t *rb = c.xs + (uint32_t)(pos - c.sl32);
+    const uint8_t *const rb0 = rb;
+    const uint8_t *const rlim = rb + (lim - pos);
+    // Row index of target u on byte b (kEnc8 rows stop at n_states - 1; the
+    // row read for u = 255 is never used).
+    auto index = [&](uint32_t u, uint32_t b) __attribute__((always_inline)) -> uint32_t {
+        if constexpr (ENC == kEnc8D) return (u << 8) | b;
+        else return ((u < rmax ? u : rmax) << 8) | b;
+    };
+    // Dead bit of table index i in bit 0 of the result (kEnc8: none).
+    auto dead_of = [&](uint32_t i) __attribute__((always_inline)) -> uint32_t {
+        if constexpr (ENC == kEnc8D) return dead[i >> 5] >> (i & 31);
+        else return 0u;
+    };
+    const uint32_t i0 = index((uint32_t)s, rb[0]);
+    uint32_t u = tb[i0];
+    uint32_t d = dead_of(i0);
+    uint32_t b2 = rb[1];
+    const uint32_t r0 = act && rb < rlim ? 1u : 0u;
+    uint32_t run = r0;
+    while (__any(run != 0)) {
+        const uint32_t f = fl[u];
+        const uint32_t i = index(u, b2);
+        const uint32_t un = tb[i];
+        const uint32_t dn = dead_of(i);
+        const uint32_t b3 = rb[2];
+        // the four reads leave together: nothing below may move above them
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t ok = (run & f) & ~d & 1u;  // flags are 0, kLive or kLive | kFinal
+        const uint32_t fin = ok & (f >> 1);
+        if (__any(fin != 0)) {
+            if (fin) c.emit(start, p0 + (int32_t)(rb - rb0), (int)u, k);
+        }
+        s = ok ? (int)u : s;
+        rb += ok;
+        run = rb < rlim ? ok : 0u;
+        u = un;
+        d = dn;
+        b2 = b3;
+    }
+    const int32_t walked = (int32_t)(rb - rb0);
+    pos = p0 + walked;
+    // A walk that started is still live exactly when it reached lim.
+    const bool alive = act && pos >= lim;
+    c.X += walked;
+    c.T += r0 ? walked + (alive ? 0 : 1) : 0;
+    if (alive && pos >= c.n32) c.carry(start, s);
+    return alive && pos < c.n32;
+}
+
 // The full walk of one start reading the input through the cache hierarchy;
 // counts its matches, or writes them from output index `at` when write.
 // With `work`, adds its instance-steps and live steps to work[0] and work[1].
@@ -565,7 +636,11 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a, DfaDefer d) {
                     if (act && (c.flag(s1) & kFinal)) c.emit(i, i, s1, km);
                     int32_t pos = i + 1;
                     if (act && pos >= n32) c.carry(i, s1);
-                    const bool park = advance_staged(c, act && pos < n32, i, s1, pos, km, lim);
+                    bool park;
+                    if constexpr (kId && (ENC == kEnc8 || ENC == kEnc8D))
+                        park = advance_staged8(c, act && pos < n32, i, s1, pos, km, lim);
+                    else
+                        park = advance_staged(c, act && pos < n32, i, s1, pos, km, lim);
                     if (qcount > QW - 64 && __any(park)) {
                         // Too many walks wait for the next window: move them
                         // to memory (they finish at the end of the slice).

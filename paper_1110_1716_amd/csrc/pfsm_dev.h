@@ -98,6 +98,9 @@ constexpr int kDfaMatchCap = 1024;             // LDS match buffer per workgroup
 constexpr int kDfaSpill = 4096;                // walks a workgroup can park in memory per segment
 constexpr int kDfaLdsLimit = 159 * 1024;       // dynamic LDS: 160 KiB per CU less the static variables
 constexpr int kDfaTableBudget = 96 * 1024;     // resident table bytes
+// Flag bytes kept in LDS for kEnc8: entries from n_states on are zero, so
+// the "no transition" value 255 reads as not live.
+constexpr int kDfaFlags8 = 256;
 constexpr int kDfaHotBudget = 48 * 1024;       // cached rows when not resident
 
 // How the transition table is read.  Resident encodings keep the whole

@@ -235,10 +235,10 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s, bool in_place = false) {
     std::vector<int16_t> first_slot(256, -1);
     int n_hot = 0;
     int enc = -1;
-    auto lds_total = [&](int64_t tab_bytes, bool resident) {
+    auto lds_total = [&](int64_t tab_bytes, bool resident, int64_t flag_bytes) {
         int64_t off = align16(kDfaLdsFixed);
         if (resident) {
-            off = align16(off + N);
+            off = align16(off + flag_bytes);
             off = align16(off + (N + 1) * 4);
             off = align16(off + (int64_t)lab.size() * 4);
         }
@@ -248,11 +248,11 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s, bool in_place = false) {
         return off + kDfaWaves * kDfaList * 4;
     };
     const int64_t bytes8 = ns, bytes8d = ((ns + 3) & ~3ll) + (ns + 31) / 32 * 4, bytes16 = ns * 2;
-    if (N <= 255 && bytes8 <= budget && lds_total(bytes8, true) <= kDfaLdsLimit) {
+    if (N <= 255 && bytes8 <= budget && lds_total(bytes8, true, kDfaFlags8) <= kDfaLdsLimit) {
         enc = kEnc8;
         res.resize(ns);
         for (int64_t i = 0; i < ns; ++i) res[i] = dl[i] < 0 ? 255 : (uint8_t)dl[i];
-    } else if (N == 256 && bytes8d <= budget && lds_total(bytes8d, true) <= kDfaLdsLimit) {
+    } else if (N == 256 && bytes8d <= budget && lds_total(bytes8d, true, N) <= kDfaLdsLimit) {
         enc = kEnc8D;
         const int64_t dead_off = (ns + 3) & ~3ll;
         res.assign(bytes8d, 0);
@@ -261,7 +261,7 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s, bool in_place = false) {
             if (dl[i] < 0) dead[i >> 5] |= 1u << (i & 31);
             else res[i] = (uint8_t)dl[i];
         }
-    } else if (N <= 32767 && bytes16 <= budget && lds_total(bytes16, true) <= kDfaLdsLimit) {
+    } else if (N <= 32767 && bytes16 <= budget && lds_total(bytes16, true, N) <= kDfaLdsLimit) {
         enc = kEnc16;
         res.resize(bytes16);
         int16_t *t = reinterpret_cast<int16_t *>(res.data());
@@ -301,7 +301,8 @@ int dfa_upload_caches(pfsm_t *h, hipStream_t s, bool in_place = false) {
     res.resize((res.size() + 15) / 16 * 16 + 16, 0);  // whole 16-byte copies
     const bool resident = enc == kEnc8 || enc == kEnc8D || enc == kEnc16;
     h->off_flags = align16(kDfaLdsFixed);
-    h->off_laboff = align16(h->off_flags + (resident ? N : 0));
+    const int flag_bytes = enc == kEnc8 ? kDfaFlags8 : N;
+    h->off_laboff = align16(h->off_flags + (resident ? flag_bytes : 0));
     h->off_lab = align16(h->off_laboff + (resident ? (N + 1) * 4 : 0));
     h->off_tab = align16(h->off_lab + (resident ? (int)lab.size() * 4 : 0));
     h->off_q = align16(h->off_tab + (int)res.size());
