@@ -730,7 +730,7 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a, DfaDefer d) {
             int *hist = reinterpret_cast<int *>(qall);
             int *base = hist + 1024;
             int *fill = base + 1024;
-            int *memb = fill + 1024;
+            uint32_t *memb = reinterpret_cast<uint32_t *>(fill + 1024);  // keys by bucket
             for (int j = tid; j < 1024; j += NT) {
                 hist[j] = 0;
                 fill[j] = 0;
@@ -758,15 +758,18 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a, DfaDefer d) {
             }
             __syncthreads();
             for (int e = tid; e < m; e += NT) {
-                const int bk = mkey[e] >> 22;
-                memb[base[bk] + atomicAdd(&fill[bk], 1)] = e;
+                const uint32_t mk = mkey[e];
+                memb[base[mk >> 22] + atomicAdd(&fill[mk >> 22], 1)] = mk;
             }
             __syncthreads();
             for (int e = tid; e < m; e += NT) {
                 const uint32_t mk = mkey[e];
                 const int bk = mk >> 22;
-                int rank = base[bk];
-                for (int j = base[bk]; j < base[bk] + hist[bk]; ++j) rank += mkey[memb[j]] < mk;
+                const int lo = base[bk], hi = lo + hist[bk];
+                int rank = lo;
+                // the bucket's keys, read independently of one another
+#pragma unroll 4
+                for (int j = lo; j < hi; ++j) rank += memb[j] < mk;
                 const long long at = defer ? dat_s + rank : at0 + rank;
                 if (defer || at < a.cap) {
                     MatchOut *p = defer ? &d.stage[at] : &a.out[at];
