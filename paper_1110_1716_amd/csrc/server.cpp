@@ -7,7 +7,9 @@
 // estimate) into a free slot and enqueues the whole batch on that slot's
 // stream (planning, one scan launch per automaton, offsets, gather; see
 // batch.hip), then goes on admitting into the other slot while the first
-// batch runs.  When a slot's batch is done its matches are copied back, the
+// batch runs.  The slots' kernels run in launch order, so batches finish in
+// turn and each slot is refilled while the other computes.  When a slot's
+// batch is done its matches are copied back, the
 // slot takes its next batch, and only then are the matches handed to the
 // waiting callers.  A batch whose output outgrows the
 // estimate is run again at the exact size (the total is known by then).
@@ -213,6 +215,7 @@ class OutPool {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    hipEvent_t kdone = nullptr;  // the batch's kernels have ended
     bool busy = false;
     std::vector<Req *> reqs;
     int64_t bytes = 0;    // input bytes of this batch
@@ -230,8 +233,10 @@ struct Slot {
             b->release();
         h_out.reset();
         if (ev) (void)hipEventDestroy(ev);
+        if (kdone) (void)hipEventDestroy(kdone);
         if (stream) (void)hipStreamDestroy(stream);
         ev = nullptr;
+        kdone = nullptr;
         stream = nullptr;
     }
 };
@@ -251,6 +256,7 @@ struct pfsm_server {
     int64_t next_id = 1;
     bool stop = false;
     Slot slots[kSlots];
+    hipEvent_t last_kdone = nullptr;  // kernels of the batch launched last (worker thread only)
     std::thread worker;
     int64_t inflight = 0;  // bytes charged to busy slots (worker thread only)
     pfsm_server_stats st{};
@@ -337,10 +343,17 @@ struct pfsm_server {
         if (pos) HIP_TRY(hipMemcpyAsync(sl.d_data.p, sl.h_data.p, pos, hipMemcpyHostToDevice, sl.stream));
         HIP_TRY(hipMemcpyAsync(sl.d_off.p, sl.h_off.p, 8 * (nr + 1), hipMemcpyHostToDevice, sl.stream));
         HIP_TRY(hipMemcpyAsync(sl.d_aut.p, sl.h_aut.p, 4 * nr, hipMemcpyHostToDevice, sl.stream));
+        // Batches compute in launch order: this batch's kernels start when
+        // those of the batch launched before it have ended (its input copy
+        // still overlaps them).  Batches then finish one after another, and
+        // the worker refills each slot while the next batch computes.
+        if (last_kdone && last_kdone != sl.kdone) HIP_TRY(hipStreamWaitEvent(sl.stream, last_kdone, 0));
         if ((rc = batch_run(hs.data(), (int32_t)hs.size(), sl.d_data.as<uint8_t>(), sl.d_off.as<int64_t>(),
                             sl.d_aut.as<int32_t>(), (int32_t)nr, sl.d_out.as<MatchOut>(), sl.out_cap,
                             sl.d_moff.as<int64_t>(), sl.stream, &sl.run)))
             return rc;
+        HIP_TRY(hipEventRecord(sl.kdone, sl.stream));
+        last_kdone = sl.kdone;
         HIP_TRY(hipMemcpyAsync(sl.h_moff.p, sl.d_moff.p, 8 * (nr + 1), hipMemcpyDeviceToHost, sl.stream));
         HIP_TRY(hipMemcpyAsync(sl.h_info.p, sl.run.info, sizeof(BatchInfo), hipMemcpyDeviceToHost, sl.stream));
         if (sl.out_cap > 0)
@@ -524,6 +537,7 @@ int pfsm_server_create(pfsm_server_t **out, pfsm_t *const *hs, int32_t n_automat
     for (Slot &sl : sv->slots) {
         HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&sl.kdone, hipEventDisableTiming));
     }
     pfsm_server *p = sv.get();
     sv->worker = std::thread([p] { p->loop(); });
