@@ -57,6 +57,18 @@ def test_cfg1_full(P):
     check(P, wl.automaton, wl.data)
 
 
+@pytest.mark.parametrize("n_states, p_dead", [(3, 0.2), (254, 0.5), (255, 0.5), (255, 0.9), (256, 0.5), (256, 0.9)])
+def test_byte_tables_at_the_8bit_boundary(P, n_states, p_dead):
+    # Byte-wide tables of at most 255 states store "no transition" as 255,
+    # one past the last state at 255 states; 256 states keep a dead bit per
+    # entry.  Walks of every length over a ragged input: matches, T and X.
+    rng = np.random.default_rng(1000 + n_states + int(100 * p_dead))
+    fsm = W.random_table_dfa(rng, n_states, 256, p_dead, min(n_states - 1, 8))
+    x = rng.integers(0, 256, 70001, dtype=np.uint8)
+    ref = check(P, fsm, x)
+    assert len(ref) > 0
+
+
 @pytest.mark.parametrize("seed", [2, 21])
 def test_cfg2_full(P, seed):
     wl = W.cfg2(seed=seed)
