@@ -620,9 +620,13 @@ __global__ __launch_bounds__(NT) void dfa_scan_kernel(DfaArgs a, DfaDefer d) {
                 c.X += cnt;
                 int total;
                 const int ex = wave_excl_small(cnt, total);
+                // Every candidate is written: survivors at their rank, the
+                // others to a slot past the survivors (the last slot is free
+                // unless every candidate survived, and then none is dropped).
+                const int spare = total + lane < kDfaList - 1 ? total + lane : kDfaList - 1;
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    if ((lm >> k) & 1u) lst[ex + __popc(lm & ((1u << k) - 1u))] = ent8[k];
+                    lst[((lm >> k) & 1u) ? ex + __popc(lm & ((1u << k) - 1u)) : spare] = ent8[k];
                 __builtin_amdgcn_wave_barrier();
                 for (int e0 = 0; e0 < total; e0 += 64) {
                     const int e = e0 + lane;
