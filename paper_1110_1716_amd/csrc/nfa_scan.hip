@@ -1015,9 +1015,14 @@ __global__ __launch_bounds__(NT, 2) void nfa_scan_kernel(NfaArgs a, DfaDefer d) 
                 const int cnt = __popc(lm);
                 int total;
                 const int ex = wave_excl_small(cnt, total);
+                // Every candidate is written: listed starts at their rank, the
+                // others past them (fewer than 64 entries wait before a half
+                // is added, so the list's last slot is free unless every
+                // candidate is listed, and then none is dropped).
+                const int spare = lcount + total + lane < LC - 1 ? lcount + total + lane : LC - 1;
 #pragma unroll
                 for (int k8 = 0; k8 < 8; ++k8)
-                    if ((lm >> k8) & 1u) lst[lcount + ex + __popc(lm & ((1u << k8) - 1u))] = ent8[k8];
+                    lst[((lm >> k8) & 1u) ? lcount + ex + __popc(lm & ((1u << k8) - 1u)) : spare] = ent8[k8];
                 lcount += total;
                 __builtin_amdgcn_wave_barrier();
                 const bool last = h == 1 && wbase + W >= own_hi;
