@@ -57,6 +57,9 @@ def test_dfa_settings_identical(P, name):
             assert P.pfsm_get_option(h, P.PFSM_OPT_SEGMENT) == seg
             if budget == 0:
                 assert P.pfsm_get_option(h, P.PFSM_OPT_RESIDENT_TABLE) == 0
+            elif name in ("cfg1", "cfg2"):
+                # the default layout keeps tables of up to 256 states in LDS
+                assert P.pfsm_get_option(h, P.PFSM_OPT_RESIDENT_TABLE) == 1
             scan_equal(P, h, x, ref)
     finally:
         h.free()
